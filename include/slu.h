@@ -1,0 +1,193 @@
+/*
+ * slu.h -- C ABI of the MI355X blocked sparse LU with structure-aware
+ * irregular blocking.
+ *
+ * The library factors a sparse matrix A (n x n, CSR) as
+ *     A[perm][:, perm] = L U,
+ * L unit lower triangular, U upper triangular, no row exchanges, and solves
+ * A X = B and A^T X = B with the factors.  The work splits into
+ *
+ *   analyze (host, once per pattern): validation, fill-reducing ordering,
+ *     symbolic fill to a structurally symmetric pattern S (Section 1 phase 2,
+ *     Section 4.2), the diagonal block pointer (Algorithm 2), the sampled
+ *     irregular blocking (Algorithm 3) or a regular blocking (Section 3.2),
+ *     and the block storage plan and per-level task lists for the numeric
+ *     phase;
+ *   factor (device, HIP kernels for gfx950): value scatter, then for every
+ *     level i of the right-looking blocked LU (Algorithm 1, Section 2.2):
+ *     GETRF of the diagonal block, GESSM / TSTRF of the U and L panels and
+ *     SSSSM Schur updates of the trailing blocks;
+ *   solve (device): forward/backward block sweeps with L and U (or U^T, L^T).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: SLU_OK (0) on success, a negative SLU_ERR_* code for an
+ *   invalid argument or a runtime failure, SLU_ZERO_PIVOT (> 0) when the
+ *   numeric factorization met a zero or non-finite pivot (slu_get_info then
+ *   reports the permuted column).  slu_error_string() names every code.
+ * - Host arrays are read during the call only; the caller keeps ownership.
+ * - Device pointers are plain HIP device addresses on the current device.
+ *   The library never allocates device memory: the caller provides one
+ *   workspace (slu_workspace_size / slu_bind_workspace) and every value,
+ *   right-hand side and solution buffer.
+ * - Streams: every device entry point takes a hipStream_t (as void*, NULL
+ *   meaning the legacy default stream) and is stream-ordered.  slu_factor
+ *   waits for its stream once at the end to read the pivot status.
+ * - A handle is not thread-safe; distinct handles are independent.
+ * - Index types: rowptr int64, column / row indices int32, n < 2^31.
+ */
+#ifndef SLU_H
+#define SLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slu_handle slu_handle;
+
+/* return codes */
+#define SLU_OK 0
+#define SLU_ZERO_PIVOT 1          /* zero / non-finite pivot; see slu_info   */
+#define SLU_ERR_ARG (-1)          /* null pointer, bad option, bad size      */
+#define SLU_ERR_ROWPTR (-2)       /* rowptr[0] != 0 or not monotone          */
+#define SLU_ERR_COLIDX (-3)       /* a column index outside [0, n)           */
+#define SLU_ERR_UNSORTED (-4)     /* columns of a row unsorted or duplicated */
+#define SLU_ERR_PERM (-5)         /* user permutation is not a permutation  */
+#define SLU_ERR_STATE (-6)        /* call out of order (e.g. no workspace)   */
+#define SLU_ERR_WORKSPACE (-7)    /* workspace too small or misaligned       */
+#define SLU_ERR_HIP (-8)          /* a HIP runtime call failed               */
+#define SLU_ERR_NOMEM (-9)        /* host allocation failed                  */
+#define SLU_ERR_NOT_FACTORED (-10) /* solve before a successful factor       */
+#define SLU_ERR_LIMIT (-11)       /* sizes beyond the library's index types  */
+
+/* orderings (the paper names none; Section 1 / Section 2.1 require one) */
+#define SLU_ORDER_NATURAL 0       /* identity                                */
+#define SLU_ORDER_GRID_ND 1       /* geometric nested dissection of a grid   */
+#define SLU_ORDER_USER 2          /* caller's permutation (new -> old)       */
+
+/* blockings */
+#define SLU_BLOCK_IRREGULAR 0     /* Algorithm 3 on the sampled Algorithm 2 curve */
+#define SLU_BLOCK_REGULAR 1       /* fixed block size (Section 3.2)          */
+
+typedef struct {
+    /* Algorithm 3 parameters: sample_points = 1000, step = 2, max_num = 3
+     * (Section 4.3); advance = 1 follows the printed loop, advance = step
+     * the "points separated by a step interval" wording. */
+    int32_t sample_points;
+    int32_t step;
+    int32_t max_num;
+    int32_t advance;
+    int32_t blocking;             /* SLU_BLOCK_IRREGULAR | SLU_BLOCK_REGULAR */
+    int32_t regular_block;        /* block size for SLU_BLOCK_REGULAR        */
+    int32_t ordering;             /* SLU_ORDER_*                             */
+    int32_t grid_dims[3];         /* nx, ny, nz for SLU_ORDER_GRID_ND; grid
+                                     point x + nx*(y + ny*z) is row/column i */
+    const int32_t *user_perm;     /* n entries for SLU_ORDER_USER; copied    */
+} slu_options;
+
+typedef struct {
+    int64_t n;
+    int64_t nnz_a;                /* entries of A                            */
+    int64_t nnz_s;                /* entries of S = nnz(L + U), both triangles */
+    int64_t nblocks;              /* p: blocks per dimension == levels       */
+    int64_t nonempty_blocks;      /* non-empty blocks of S, both triangles   */
+    int64_t ssssm_tasks;          /* (k, j) Schur-update tasks over all levels */
+    double flops;                 /* sum_k (c_k - 1) + 2 (c_k - 1)^2 on S    */
+    double flops_getrf;           /* part of flops inside diagonal blocks    */
+    double flops_panel;           /* part in the GESSM / TSTRF panel solves  */
+    double flops_ssssm;           /* part in the SSSSM Schur updates         */
+    double stored_flops;          /* flops the kernels execute incl. padding */
+    int64_t slab_bytes;           /* factor value storage inside the workspace */
+    int64_t workspace_bytes;      /* total device workspace                  */
+    int64_t zero_pivot_col;       /* permuted column of a failed pivot, or -1 */
+    int32_t factored;             /* 1 after a successful slu_factor         */
+    int32_t max_block;            /* largest block size                      */
+} slu_info;
+
+/* Fill *opt with the defaults: irregular blocking, 1000 / 2 / 3 / 1,
+ * natural ordering. */
+void slu_default_options(slu_options *opt);
+
+/* Analyze the pattern of A (host).  rowptr: int64[n+1]; colidx: int32[nnz],
+ * strictly increasing inside each row.  A structurally missing diagonal
+ * entry is added to S as an explicit zero.  On success *out receives a new
+ * handle owned by the caller (release with slu_free).  Errors:
+ * SLU_ERR_ARG, SLU_ERR_ROWPTR, SLU_ERR_COLIDX, SLU_ERR_UNSORTED,
+ * SLU_ERR_PERM, SLU_ERR_NOMEM, SLU_ERR_LIMIT. */
+int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                const slu_options *opt, slu_handle **out);
+
+/* Device bytes the handle needs (factor storage + structure + scratch). */
+int slu_workspace_size(const slu_handle *h, size_t *bytes);
+
+/* Bind a caller-owned device buffer of at least slu_workspace_size bytes,
+ * 256-byte aligned, and upload the structure into it on `stream`.  The
+ * buffer must outlive the handle's device calls. */
+int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stream);
+
+/* Numeric factorization.  values: device float64[nnz_a] in the CSR order
+ * given to slu_analyze.  Runs the value scatter and the level loop of
+ * Algorithm 1 (GETRF, GESSM, TSTRF, SSSSM) on `stream`, then waits for the
+ * stream.  Returns SLU_OK or SLU_ZERO_PIVOT. */
+int slu_factor(slu_handle *h, const double *values, void *stream);
+
+/* Solve A X = B.  B, X: device float64, column-major n x nrhs with leading
+ * dimension ld >= n; X may alias B.  Requires a successful factor. */
+int slu_solve(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld,
+              void *stream);
+
+/* Solve A^T X = B with the same factors (U^T then L^T sweeps). */
+int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs,
+                        int64_t ld, void *stream);
+
+/* Normwise backward error per right-hand side on the device,
+ * eta_c = ||b_c - op(A) x_c||_inf / (||op(A)||_inf ||x_c||_inf + ||b_c||_inf),
+ * op(A) = A or A^T.  values: device float64[nnz_a]; eta: host double[nrhs].
+ * Synchronizes `stream`. */
+int slu_backward_error(slu_handle *h, const double *values, const double *B,
+                       const double *X, int64_t nrhs, int64_t ld, int transpose,
+                       double *eta, void *stream);
+
+int slu_get_info(const slu_handle *h, slu_info *info);
+
+/* Kernel classes for per-kernel timing. */
+#define SLU_KERNEL_SCATTER 0      /* value scatter (and slab clear)          */
+#define SLU_KERNEL_GETRF 1
+#define SLU_KERNEL_PANEL 2        /* GESSM + TSTRF                           */
+#define SLU_KERNEL_SSSSM 3
+#define SLU_NUM_KERNELS 4
+
+/* Enable (1) or disable (0) per-kernel timing.  While enabled, slu_factor
+ * records a HIP event pair on its stream around every kernel launch and
+ * adds the elapsed times per kernel class; slu_get_kernel_times reports the
+ * totals of the last slu_factor.  Timing adds host-side event work between
+ * launches; it does not change results. */
+int slu_set_profiling(slu_handle *h, int enable);
+/* ms[SLU_NUM_KERNELS]: summed kernel milliseconds of the last factor;
+ * launches[SLU_NUM_KERNELS]: launch counts. */
+int slu_get_kernel_times(const slu_handle *h, double *ms, int64_t *launches);
+
+/* Structure accessors (host arrays sized as stated; for parity checks). */
+int slu_get_perm(const slu_handle *h, int32_t *perm);            /* n       */
+int slu_get_blockptr(const slu_handle *h, int64_t *blockptr);    /* n + 1 (Algorithm 2) */
+int slu_get_blocking(const slu_handle *h, int64_t *ptr);         /* p + 1 (Algorithm 3) */
+/* Lower triangle of S in CSC with the diagonal first in every column:
+ * colptr int64[n+1], rowidx int32[colptr[n]]. */
+int slu_get_pattern(const slu_handle *h, int64_t *colptr, int32_t *rowidx);
+
+/* Copy the factors to host arrays laid out on the lower CSC of S
+ * (slu_get_pattern): for entry e of column k at row r > k,
+ * lval[e] = L(r, k) and uval[e] = U(k, r); lval[colptr[k]] = U(k, k) and
+ * uval[colptr[k]] = U(k, k).  Synchronizes `stream`. */
+int slu_get_factors(const slu_handle *h, double *lval, double *uval, void *stream);
+
+const char *slu_error_string(int code);
+void slu_free(slu_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLU_H */

@@ -1,0 +1,179 @@
+"""MI355X blocked sparse LU with structure-aware irregular blocking.
+
+Thin Python binding of the C ABI (``include/slu.h``).  Host arrays are numpy;
+device buffers are torch tensors used only for memory and streams.  All the
+numerical work runs in the HIP kernels of ``libslu.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import (SLU_BLOCK_IRREGULAR, SLU_BLOCK_REGULAR, SLU_ORDER_GRID_ND,
+                   SLU_ORDER_NATURAL, SLU_ORDER_USER, SluError, ZeroPivot, check, lib)
+
+__all__ = ["SparseLU", "SluError", "ZeroPivot", "lib"]
+
+
+def _vp(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else ctypes.c_void_p(0)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class SparseLU:
+    """One analyzed pattern: ``slu_analyze`` at construction, then
+    ``bind`` (workspace), ``factor``, ``solve`` / ``solve_transpose``."""
+
+    def __init__(self, n, rowptr, colidx, ordering="natural", grid_dims=None, perm=None,
+                 blocking="irregular", block_size=0, sample_points=1000, step=2, max_num=3,
+                 advance=1):
+        self.n = int(n)
+        self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self._colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+        opt = _abi.slu_options()
+        lib.slu_default_options(ctypes.byref(opt))
+        opt.sample_points, opt.step, opt.max_num, opt.advance = sample_points, step, max_num, advance
+        opt.blocking = {"irregular": SLU_BLOCK_IRREGULAR, "regular": SLU_BLOCK_REGULAR}[blocking]
+        opt.regular_block = int(block_size)
+        self._perm_in = None
+        if ordering == "natural":
+            opt.ordering = SLU_ORDER_NATURAL
+        elif ordering == "grid_nd":
+            opt.ordering = SLU_ORDER_GRID_ND
+            dims = tuple(int(v) for v in grid_dims) + (1,) * (3 - len(grid_dims))
+            for d in range(3):
+                opt.grid_dims[d] = dims[d]
+        elif ordering == "user":
+            opt.ordering = SLU_ORDER_USER
+            self._perm_in = np.ascontiguousarray(perm, dtype=np.int32)
+            opt.user_perm = self._perm_in.ctypes.data
+        else:
+            raise ValueError("unknown ordering %r" % ordering)
+        h = ctypes.c_void_p()
+        check(lib.slu_analyze(self.n, _vp(self._rowptr), _vp(self._colidx), ctypes.byref(opt),
+                              ctypes.byref(h)), "slu_analyze")
+        self._h = h
+        self._ws = None
+
+    # ---------------------------------------------------------------- info
+    def info(self):
+        inf = _abi.slu_info()
+        check(lib.slu_get_info(self._h, ctypes.byref(inf)), "slu_get_info")
+        return {name: getattr(inf, name) for name, _ in _abi.slu_info._fields_}
+
+    def perm(self):
+        out = np.empty(self.n, dtype=np.int32)
+        check(lib.slu_get_perm(self._h, _vp(out)), "slu_get_perm")
+        return out
+
+    def blockptr(self):
+        out = np.empty(self.n + 1, dtype=np.int64)
+        check(lib.slu_get_blockptr(self._h, _vp(out)), "slu_get_blockptr")
+        return out
+
+    def blocking(self):
+        out = np.empty(self.info()["nblocks"] + 1, dtype=np.int64)
+        check(lib.slu_get_blocking(self._h, _vp(out)), "slu_get_blocking")
+        return out
+
+    def pattern(self):
+        colptr = np.empty(self.n + 1, dtype=np.int64)
+        nnz_s = self.info()["nnz_s"]
+        rowidx = np.empty((nnz_s + self.n) // 2, dtype=np.int32)
+        check(lib.slu_get_pattern(self._h, _vp(colptr), _vp(rowidx)), "slu_get_pattern")
+        return colptr, rowidx
+
+    def workspace_size(self):
+        sz = ctypes.c_size_t()
+        check(lib.slu_workspace_size(self._h, ctypes.byref(sz)), "slu_workspace_size")
+        return int(sz.value)
+
+    # -------------------------------------------------------------- device
+    def bind(self, device="cuda", stream=None, workspace=None):
+        import torch
+        nbytes = self.workspace_size()
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        check(lib.slu_bind_workspace(self._h, _dptr(workspace), workspace.numel(), _stream(stream)),
+              "slu_bind_workspace")
+        self._ws = workspace
+        return self
+
+    def factor(self, values, stream=None):
+        rc = lib.slu_factor(self._h, _dptr(values), _stream(stream))
+        if rc == _abi.SLU_ZERO_PIVOT:
+            raise ZeroPivot(self.info()["zero_pivot_col"])
+        check(rc, "slu_factor")
+
+    def _solve(self, fn, B, X, stream):
+        import torch
+        vec = B.dim() == 1
+        Bm = B.reshape(-1, 1) if vec else B
+        nrhs = Bm.shape[1]
+        # column-major n x nrhs: a (nrhs, n) row-major tensor viewed transposed
+        Bc = Bm.t().contiguous()
+        if X is None:
+            Xc = torch.empty_like(Bc)
+        else:
+            Xc = X.reshape(-1, 1).t().contiguous() if vec else X.t().contiguous()
+        check(fn(self._h, _dptr(Bc), _dptr(Xc), nrhs, self.n, _stream(stream)), fn.__name__)
+        out = Xc.t()
+        return out.reshape(-1) if vec else out
+
+    def solve(self, B, X=None, stream=None):
+        return self._solve(lib.slu_solve, B, X, stream)
+
+    def solve_transpose(self, B, X=None, stream=None):
+        return self._solve(lib.slu_solve_transpose, B, X, stream)
+
+    def backward_error(self, values, B, X, transpose=False, stream=None):
+        vec = B.dim() == 1
+        Bc = (B.reshape(-1, 1) if vec else B).t().contiguous()
+        Xc = (X.reshape(-1, 1) if vec else X).t().contiguous()
+        nrhs = Bc.shape[0]
+        eta = np.empty(nrhs, dtype=np.float64)
+        check(lib.slu_backward_error(self._h, _dptr(values), _dptr(Bc), _dptr(Xc), nrhs, self.n,
+                                     1 if transpose else 0, _vp(eta), _stream(stream)),
+              "slu_backward_error")
+        return eta
+
+    def factors(self, stream=None):
+        """(lval, uval) on the lower CSC of S (see ``slu_get_factors``)."""
+        colptr, _ = self.pattern()
+        lv = np.empty(int(colptr[-1]), dtype=np.float64)
+        uv = np.empty(int(colptr[-1]), dtype=np.float64)
+        check(lib.slu_get_factors(self._h, _vp(lv), _vp(uv), _stream(stream)), "slu_get_factors")
+        return lv, uv
+
+    def set_profiling(self, enable=True):
+        check(lib.slu_set_profiling(self._h, 1 if enable else 0), "slu_set_profiling")
+
+    def kernel_times(self):
+        """{kernel: (ms, launches)} of the last factor with profiling on."""
+        ms = np.zeros(len(_abi.KERNELS), dtype=np.float64)
+        nl = np.zeros(len(_abi.KERNELS), dtype=np.int64)
+        check(lib.slu_get_kernel_times(self._h, _vp(ms), _vp(nl)), "slu_get_kernel_times")
+        return {k: (float(ms[i]), int(nl[i])) for i, k in enumerate(_abi.KERNELS)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.slu_free(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,504 @@
+// Host-side analysis: validation, ordering, symbolic fill, Algorithm 2,
+// Algorithm 3 and the block storage plan used by the device kernels.
+#include "analyze.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace slu {
+
+// ---------------------------------------------------------------- ordering
+// The paper requires a fill-reducing reordering (Section 1, Section 2.1,
+// Fig. 2) without naming one.  Geometric nested dissection of a grid with a
+// fixed rule: cut the longest axis (lowest axis on ties) at lo + (hi-lo)/2;
+// order the first part, the second part, then the separator plane; boxes of
+// volume <= 8 or with every extent <= 2 are listed in grid-index order.
+namespace {
+struct Box {
+    int32_t lo[3], hi[3];
+};
+
+void box_points(const Box &bx, int32_t nx, int32_t ny, std::vector<int32_t> *out) {
+    for (int32_t z = bx.lo[2]; z < bx.hi[2]; ++z)
+        for (int32_t y = bx.lo[1]; y < bx.hi[1]; ++y)
+            for (int32_t x = bx.lo[0]; x < bx.hi[0]; ++x)
+                out->push_back(x + nx * (y + ny * z));
+}
+
+void nd_rec(const Box &bx, int32_t nx, int32_t ny, std::vector<int32_t> *out) {
+    int64_t ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = (int64_t)bx.hi[d] - bx.lo[d];
+    if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) return;
+    int64_t vol = ext[0] * ext[1] * ext[2];
+    int64_t mx = std::max(ext[0], std::max(ext[1], ext[2]));
+    if (vol <= 8 || mx <= 2) {
+        box_points(bx, nx, ny, out);
+        return;
+    }
+    int d = 0;
+    for (int e = 1; e < 3; ++e)
+        if (ext[e] > ext[d]) d = e;
+    int32_t m = bx.lo[d] + (bx.hi[d] - bx.lo[d]) / 2;
+    Box a = bx, c = bx, s = bx;
+    a.hi[d] = m;
+    c.lo[d] = m + 1;
+    s.lo[d] = m;
+    s.hi[d] = m + 1;
+    nd_rec(a, nx, ny, out);
+    nd_rec(c, nx, ny, out);
+    box_points(s, nx, ny, out);
+}
+}  // namespace
+
+void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *perm) {
+    perm->clear();
+    perm->reserve((size_t)nx * ny * nz);
+    Box root{{0, 0, 0}, {nx, ny, nz}};
+    nd_rec(root, nx, ny, perm);
+}
+
+// ------------------------------------------------------------ Algorithm 3
+// Readings: Sp = min(sample_points, N) intervals, sample s at row
+// floor(s*N/Sp); the loop runs while i + step <= Sp advancing by `advance`;
+// the threshold step/Sp is compared exactly as
+// (blockptr[pos(i+step)] - blockptr[pos(i)]) * Sp >= step * blockptr[N];
+// N closes the last block.
+void irregular_blocking(const std::vector<int64_t> &blockptr, int sample_points, int step,
+                        int max_num, int advance, std::vector<int64_t> *ptr) {
+    ptr->clear();
+    const int64_t N = (int64_t)blockptr.size() - 1;
+    ptr->push_back(0);
+    if (N <= 0) return;
+    const int64_t sp = std::min<int64_t>(sample_points, N);
+    auto pos = [&](int64_t s) { return (int64_t)(((__int128)s * N) / sp); };
+    const __int128 total = blockptr[N];
+    int64_t l = 0;
+    for (int64_t i = 0; i + step <= sp; i += advance) {
+        const int64_t lo = blockptr[pos(i)];
+        const int64_t hi = blockptr[pos(i + step)];
+        if ((__int128)(hi - lo) * sp >= (__int128)step * total) {  // dense region
+            ptr->push_back(pos(i + step));
+            l = 0;
+        } else if (l >= max_num) {                                 // block would grow too large
+            ptr->push_back(pos(i + step));
+            l = 0;
+        } else {
+            ++l;
+        }
+    }
+    if (ptr->back() != N) ptr->push_back(N);
+}
+
+// ---------------------------------------------------------------- analysis
+namespace {
+
+int validate(int64_t n, const int64_t *rowptr, const int32_t *colidx) {
+    if (n < 0) return SLU_ERR_ARG;
+    if (n >= ((int64_t)1 << 31) - 1) return SLU_ERR_LIMIT;
+    if (!rowptr) return SLU_ERR_ARG;
+    if (rowptr[0] != 0) return SLU_ERR_ROWPTR;
+    for (int64_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return SLU_ERR_ROWPTR;
+    if (rowptr[n] > 0 && !colidx) return SLU_ERR_ARG;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            const int32_t c = colidx[q];
+            if (c < 0 || c >= n) return SLU_ERR_COLIDX;
+            if (q > rowptr[i] && c <= colidx[q - 1]) return SLU_ERR_UNSORTED;
+        }
+    }
+    return SLU_OK;
+}
+
+// Pattern of B = P0[perm][:, perm] with P0 = A + A^T + I, as sorted CSR.
+void permuted_symmetric(const Analysis &an, std::vector<int64_t> *bp, std::vector<int32_t> *bi) {
+    const int64_t n = an.n;
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t r = an.iperm[i];
+        cnt[r + 1] += 1;  // diagonal
+        for (int64_t q = an.a_rowptr[i]; q < an.a_rowptr[i + 1]; ++q) {
+            const int64_t c = an.iperm[an.a_colidx[q]];
+            if (c == r) continue;
+            cnt[r + 1] += 1;
+            cnt[c + 1] += 1;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> tmp(cnt[n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t r = an.iperm[i];
+        tmp[fill[r]++] = (int32_t)r;
+        for (int64_t q = an.a_rowptr[i]; q < an.a_rowptr[i + 1]; ++q) {
+            const int64_t c = an.iperm[an.a_colidx[q]];
+            if (c == r) continue;
+            tmp[fill[r]++] = (int32_t)c;
+            tmp[fill[c]++] = (int32_t)r;
+        }
+    }
+    bp->assign(n + 1, 0);
+    bi->clear();
+    bi->reserve(tmp.size());
+    for (int64_t r = 0; r < n; ++r) {
+        auto b = tmp.begin() + cnt[r], e = tmp.begin() + cnt[r + 1];
+        std::sort(b, e);
+        auto u = std::unique(b, e);
+        bi->insert(bi->end(), b, u);
+        (*bp)[r + 1] = (int64_t)bi->size();
+    }
+}
+
+// Lower CSC of the fill of symmetric pattern B: Struct(L_k) = Adj_{>k}(k)
+// union (Struct(L_c) minus {k}) over the elimination-tree children c of k.
+void symbolic_fill(int64_t n, const std::vector<int64_t> &bp, const std::vector<int32_t> &bi,
+                   std::vector<int64_t> *colptr, std::vector<int32_t> *rowidx) {
+    colptr->assign(n + 1, 0);
+    rowidx->clear();
+    rowidx->reserve(bi.size());
+    std::vector<int32_t> mark(n, -1), head(n, -1), next(n, -1), list;
+    for (int64_t k = 0; k < n; ++k) {
+        list.clear();
+        mark[k] = (int32_t)k;
+        for (int64_t q = bp[k]; q < bp[k + 1]; ++q) {
+            const int32_t r = bi[q];
+            if (r > k && mark[r] != k) {
+                mark[r] = (int32_t)k;
+                list.push_back(r);
+            }
+        }
+        for (int32_t c = head[k]; c >= 0; c = next[c]) {
+            // skip the diagonal and the first sub-diagonal row (== k)
+            for (int64_t q = (*colptr)[c] + 2; q < (*colptr)[c + 1]; ++q) {
+                const int32_t r = (*rowidx)[q];
+                if (mark[r] != k) {
+                    mark[r] = (int32_t)k;
+                    list.push_back(r);
+                }
+            }
+        }
+        std::sort(list.begin(), list.end());
+        rowidx->push_back((int32_t)k);
+        rowidx->insert(rowidx->end(), list.begin(), list.end());
+        (*colptr)[k + 1] = (int64_t)rowidx->size();
+        if (!list.empty()) {
+            const int32_t par = list[0];
+            next[k] = head[par];
+            head[par] = (int32_t)k;
+        }
+    }
+}
+
+inline int64_t align32(int64_t x) { return (x + 31) & ~(int64_t)31; }
+
+int32_t lower_pos(const int32_t *b, int32_t len, int32_t v) {
+    const int32_t *it = std::lower_bound(b, b + len, v);
+    if (it == b + len || *it != v) return -1;
+    return (int32_t)(it - b);
+}
+
+}  // namespace
+
+int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &opt,
+            Analysis *out) {
+    int rc = validate(n, rowptr, colidx);
+    if (rc != SLU_OK) return rc;
+    if (opt.sample_points < 1 || opt.step < 1 || opt.max_num < 0 || opt.advance < 1)
+        return SLU_ERR_ARG;
+    if (opt.blocking != SLU_BLOCK_IRREGULAR && opt.blocking != SLU_BLOCK_REGULAR) return SLU_ERR_ARG;
+    if (opt.blocking == SLU_BLOCK_REGULAR && opt.regular_block < 1) return SLU_ERR_ARG;
+
+    Analysis &an = *out;
+    an = Analysis();
+    an.n = n;
+    an.opt = opt;
+    an.opt.user_perm = nullptr;
+    an.nnz_a = rowptr[n];
+    an.a_rowptr.assign(rowptr, rowptr + n + 1);
+    an.a_colidx.assign(colidx, colidx + an.nnz_a);
+
+    // ordering
+    if (opt.ordering == SLU_ORDER_NATURAL) {
+        an.perm.resize(n);
+        std::iota(an.perm.begin(), an.perm.end(), 0);
+    } else if (opt.ordering == SLU_ORDER_GRID_ND) {
+        const int64_t nx = opt.grid_dims[0], ny = opt.grid_dims[1], nz = opt.grid_dims[2];
+        if (nx < 1 || ny < 1 || nz < 1 || nx * ny * nz != n) return SLU_ERR_ARG;
+        nd_grid_order((int32_t)nx, (int32_t)ny, (int32_t)nz, &an.perm);
+    } else if (opt.ordering == SLU_ORDER_USER) {
+        if (!opt.user_perm && n > 0) return SLU_ERR_ARG;
+        an.perm.assign(opt.user_perm, opt.user_perm + n);
+    } else {
+        return SLU_ERR_ARG;
+    }
+    an.iperm.assign(n, -1);
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t v = an.perm[k];
+        if (v < 0 || v >= n || an.iperm[v] != -1) return SLU_ERR_PERM;
+        an.iperm[v] = (int32_t)k;
+    }
+
+    // symbolic fill of the permuted symmetrised pattern
+    {
+        std::vector<int64_t> bp;
+        std::vector<int32_t> bi;
+        permuted_symmetric(an, &bp, &bi);
+        symbolic_fill(n, bp, bi, &an.s_colptr, &an.s_rowidx);
+    }
+    const int64_t nnzL = an.s_colptr[n];
+
+    // Algorithm 2: blockptr[i+1] = blockptr[i] + 2*num[i] + 1 where num[r]
+    // counts the entries of S below the diagonal in row r.
+    {
+        std::vector<int64_t> num(n, 0);
+        for (int64_t k = 0; k < n; ++k)
+            for (int64_t q = an.s_colptr[k] + 1; q < an.s_colptr[k + 1]; ++q) num[an.s_rowidx[q]] += 1;
+        an.blockptr.assign(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) an.blockptr[i + 1] = an.blockptr[i] + 2 * num[i] + 1;
+    }
+
+    // blocking
+    if (opt.blocking == SLU_BLOCK_IRREGULAR) {
+        irregular_blocking(an.blockptr, opt.sample_points, opt.step, opt.max_num, opt.advance, &an.bptr);
+    } else {
+        an.bptr.clear();
+        for (int64_t r = 0; r < n; r += opt.regular_block) an.bptr.push_back(r);
+        an.bptr.push_back(n);
+        if (n == 0) an.bptr.assign(1, 0);
+    }
+    const int64_t p = (int64_t)an.bptr.size() - 1;
+    an.p = p;
+    an.bid.assign(n, 0);
+    for (int64_t i = 0; i < p; ++i) {
+        for (int64_t r = an.bptr[i]; r < an.bptr[i + 1]; ++r) an.bid[r] = (int32_t)i;
+        an.max_block = std::max<int32_t>(an.max_block, (int32_t)(an.bptr[i + 1] - an.bptr[i]));
+    }
+
+    // flop count on S (identical for every blocking), split by the block
+    // kernel that performs each operation: for pivot k of block I with
+    // n_in sub-diagonal rows inside I and n_out below it, the divisions and
+    // the updates inside I belong to GETRF, the mixed updates and the
+    // divisions below I to GESSM / TSTRF, the updates below I to SSSSM.
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t rend = an.bptr[an.bid[k] + 1];
+        int64_t nin = 0, nout = 0;
+        for (int64_t q = an.s_colptr[k] + 1; q < an.s_colptr[k + 1]; ++q) {
+            if (an.s_rowidx[q] < rend) ++nin; else ++nout;
+        }
+        const double a = (double)nin, o = (double)nout, l = a + o;
+        an.flops += l + 2.0 * l * l;
+        an.flops_getrf += a + 2.0 * a * a;
+        an.flops_panel += o + 4.0 * a * o;
+        an.flops_ssssm += 2.0 * o * o;
+    }
+
+    // per level: K_i, rows_i, segments, slab offsets
+    an.levels.assign(p, LevelDev());
+    an.posK.assign(n, -1);
+    std::vector<int32_t> mark(n, -1);
+    int64_t off = 0;
+    {
+        std::vector<int32_t> rows;
+        for (int64_t i = 0; i < p; ++i) {
+            LevelDev &L = an.levels[i];
+            const int64_t r0 = an.bptr[i], r1 = an.bptr[i + 1];
+            L.r0 = (int32_t)r0;
+            L.b = (int32_t)(r1 - r0);
+            L.Koff = (int64_t)an.K_idx.size();
+            L.Roff = (int64_t)an.R_idx.size();
+            rows.clear();
+            int32_t kap = 0;
+            for (int64_t c = r0; c < r1; ++c) {
+                const int64_t q0 = an.s_colptr[c], q1 = an.s_colptr[c + 1];
+                if (an.s_rowidx[q1 - 1] >= r1) {
+                    an.posK[c] = kap++;
+                    an.K_idx.push_back((int32_t)(c - r0));
+                }
+                for (int64_t q = q1 - 1; q > q0 && an.s_rowidx[q] >= r1; --q) {
+                    const int32_t r = an.s_rowidx[q];
+                    if (mark[r] != i) {
+                        mark[r] = (int32_t)i;
+                        rows.push_back(r);
+                    }
+                }
+            }
+            std::sort(rows.begin(), rows.end());
+            an.R_idx.insert(an.R_idx.end(), rows.begin(), rows.end());
+            L.kappa = kap;
+            L.m = (int32_t)rows.size();
+            L.seg_begin = (int32_t)an.segs.size();
+            for (size_t a = 0; a < rows.size();) {
+                const int32_t k = an.bid[rows[a]];
+                size_t e = a;
+                while (e < rows.size() && an.bid[rows[e]] == k) ++e;
+                an.segs.push_back(Segment{k, (int32_t)a, (int32_t)(e - a)});
+                a = e;
+            }
+            L.seg_end = (int32_t)an.segs.size();
+            L.offD = off;
+            off += align32((int64_t)L.b * L.b);
+            L.offP = off;
+            off += align32((int64_t)L.m * L.kappa);
+            L.offQ = off;
+            off += align32((int64_t)L.m * L.kappa);
+            an.max_gemm_k = std::max(an.max_gemm_k, kap);
+        }
+    }
+    an.slab_doubles = off;
+
+    // non-empty blocks of S (both triangles): diagonal blocks + 2 * segments
+    an.nonempty_blocks = p + 2 * (int64_t)an.segs.size();
+
+    // GETRF chunks.  Blocks up to kLdsDenseMax are one LDS-resident chunk;
+    // larger ones are factored right-looking in chunks of w columns, each
+    // with the block rows below the chunk that S couples to it.
+    std::vector<int32_t> cmark(n, 0);
+    int32_t chunk_stamp = 0;
+    for (int64_t i = 0; i < p; ++i) {
+        LevelDev &L = an.levels[i];
+        const int32_t b = L.b, r0 = L.r0;
+        L.chunk_begin = (int32_t)an.chunks.size();
+        if (b <= kLdsDenseMax) {
+            an.chunks.push_back(ChunkDev{0, b, 0, 0, (int64_t)an.chunk_rows.size()});
+            L.lds_getrf = (int32_t)((int64_t)b * b * 8);
+            an.stored_flops += 2.0 / 3.0 * (double)b * b * b;
+        } else {
+            int32_t w = 16;
+            while (w > 1 && ((int64_t)(w + b) * w + (int64_t)w * b) * 8 > kGetrfLdsBudget) w /= 2;
+            int64_t maxl = 0;
+            std::vector<int32_t> rl;
+            for (int32_t c0 = 0; c0 < b; c0 += w) {
+                const int32_t ww = std::min(w, b - c0);
+                const int32_t c1 = c0 + ww;
+                const int32_t stamp = ++chunk_stamp;
+                rl.clear();
+                for (int32_t c = c0; c < c1; ++c) {
+                    const int64_t gc = r0 + c;
+                    for (int64_t q = an.s_colptr[gc] + 1; q < an.s_colptr[gc + 1]; ++q) {
+                        const int32_t r = an.s_rowidx[q];
+                        if (r >= r0 + b) break;
+                        if (r >= r0 + c1 && cmark[r] != stamp) {
+                            cmark[r] = stamp;
+                            rl.push_back(r - r0);
+                        }
+                    }
+                }
+                std::sort(rl.begin(), rl.end());
+                an.chunks.push_back(ChunkDev{c0, ww, (int32_t)rl.size(), 0, (int64_t)an.chunk_rows.size()});
+                an.chunk_rows.insert(an.chunk_rows.end(), rl.begin(), rl.end());
+                const int64_t nr = (int64_t)rl.size();
+                maxl = std::max<int64_t>(maxl, ((int64_t)(ww + nr) * ww + (int64_t)ww * nr) * 8);
+                an.stored_flops += 2.0 * (double)nr * nr * ww + (double)(ww + nr) * ww * ww + (double)ww * ww * nr;
+            }
+            L.lds_getrf = (int32_t)maxl;
+        }
+        L.chunk_end = (int32_t)an.chunks.size();
+    }
+
+    // SSSSM tasks, maps and tiles
+    for (int64_t i = 0; i < p; ++i) {
+        LevelDev &L = an.levels[i];
+        L.task_begin = (int64_t)an.tasks.size();
+        L.tile_begin = (int64_t)an.tiles.size();
+        const int32_t *rows_i = an.R_idx.data() + L.Roff;
+        if (L.kappa > 0) {
+            an.stored_flops += 2.0 * 2.0 * (double)L.m * L.kappa * L.kappa / 2.0;
+            for (int32_t sa = L.seg_begin; sa < L.seg_end; ++sa) {
+                const Segment A = an.segs[sa];
+                const int32_t k = A.blk;
+                const LevelDev &Lk = an.levels[k];
+                for (int32_t sb = L.seg_begin; sb < L.seg_end; ++sb) {
+                    const Segment B = an.segs[sb];
+                    const int32_t j = B.blk;
+                    const LevelDev &Lj = an.levels[j];
+                    TaskDev t{};
+                    t.a0 = A.start;
+                    t.alen = A.len;
+                    t.b0 = B.start;
+                    t.blen = B.len;
+                    t.rmap = (int64_t)an.maps.size();
+                    if (k == j) {
+                        t.tgt = Lk.offD;
+                        t.rs = 1;
+                        t.cs = Lk.b;
+                        for (int32_t a = 0; a < A.len; ++a) an.maps.push_back(rows_i[A.start + a] - Lk.r0);
+                        t.cmap = (int64_t)an.maps.size();
+                        for (int32_t c = 0; c < B.len; ++c) an.maps.push_back(rows_i[B.start + c] - Lk.r0);
+                    } else if (k > j) {
+                        // L block (k, j) inside P_j: row = position in rows_j, col = position in K_j
+                        t.tgt = Lj.offP;
+                        t.rs = 1;
+                        t.cs = Lj.m;
+                        const int32_t *rows_j = an.R_idx.data() + Lj.Roff;
+                        for (int32_t a = 0; a < A.len; ++a)
+                            an.maps.push_back(lower_pos(rows_j, Lj.m, rows_i[A.start + a]));
+                        t.cmap = (int64_t)an.maps.size();
+                        for (int32_t c = 0; c < B.len; ++c) an.maps.push_back(an.posK[rows_i[B.start + c]]);
+                    } else {
+                        // U block (k, j) inside Qt_k: Qt_k[pos in rows_k, pos in K_k]
+                        t.tgt = Lk.offQ;
+                        t.rs = Lk.m;
+                        t.cs = 1;
+                        const int32_t *rows_k = an.R_idx.data() + Lk.Roff;
+                        for (int32_t a = 0; a < A.len; ++a) an.maps.push_back(an.posK[rows_i[A.start + a]]);
+                        t.cmap = (int64_t)an.maps.size();
+                        for (int32_t c = 0; c < B.len; ++c)
+                            an.maps.push_back(lower_pos(rows_k, Lk.m, rows_i[B.start + c]));
+                    }
+                    const int32_t task_id = (int32_t)an.tasks.size();
+                    an.tasks.push_back(t);
+                    const int32_t nti = (A.len + kTile - 1) / kTile, ntj = (B.len + kTile - 1) / kTile;
+                    for (int32_t ti = 0; ti < nti; ++ti)
+                        for (int32_t tj = 0; tj < ntj; ++tj) an.tiles.push_back(TileDev{task_id, (ti << 16) | tj});
+                    an.stored_flops += 2.0 * (double)nti * kTile * ntj * kTile * L.kappa;
+                }
+            }
+        }
+        L.task_end = (int64_t)an.tasks.size();
+        L.tile_end = (int64_t)an.tiles.size();
+    }
+    if ((int64_t)an.tasks.size() >= ((int64_t)1 << 31) || an.maps.size() >= ((size_t)1 << 40))
+        return SLU_ERR_LIMIT;
+
+    // slot of every entry of A in the slab
+    an.slot.assign(an.nnz_a, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t r = an.iperm[i];
+        const int32_t I = an.bid[r];
+        const LevelDev &LI = an.levels[I];
+        for (int64_t q = an.a_rowptr[i]; q < an.a_rowptr[i + 1]; ++q) {
+            const int32_t c = an.iperm[an.a_colidx[q]];
+            const int32_t J = an.bid[c];
+            const LevelDev &LJ = an.levels[J];
+            int64_t s;
+            if (I == J) {
+                s = LI.offD + (int64_t)(r - LI.r0) + (int64_t)(c - LI.r0) * LI.b;
+            } else if (I > J) {
+                const int32_t rp = lower_pos(an.R_idx.data() + LJ.Roff, LJ.m, r);
+                s = LJ.offP + rp + (int64_t)an.posK[c] * LJ.m;
+            } else {
+                const int32_t cp = lower_pos(an.R_idx.data() + LI.Roff, LI.m, c);
+                s = LI.offQ + cp + (int64_t)an.posK[r] * LI.m;
+            }
+            if (s < 0 || s >= an.slab_doubles) return SLU_ERR_LIMIT;  // cannot happen for a closed S
+            an.slot[q] = s;
+        }
+    }
+    // every map entry must address inside its target array
+    for (int64_t i = 0; i < p; ++i) {
+        const LevelDev &L = an.levels[i];
+        for (int64_t t = L.task_begin; t < L.task_end; ++t) {
+            const TaskDev &T = an.tasks[t];
+            int64_t rmax = -1, cmax = -1;
+            for (int32_t a = 0; a < T.alen; ++a) rmax = std::max<int64_t>(rmax, an.maps[T.rmap + a]);
+            for (int32_t c = 0; c < T.blen; ++c) cmax = std::max<int64_t>(cmax, an.maps[T.cmap + c]);
+            const int64_t last = T.tgt + std::max<int64_t>(rmax, 0) * T.rs + std::max<int64_t>(cmax, 0) * T.cs;
+            if (last >= an.slab_doubles || T.a0 + T.alen > L.m || T.b0 + T.blen > L.m) return SLU_ERR_LIMIT;
+        }
+    }
+    (void)nnzL;
+    return SLU_OK;
+}
+
+}  // namespace slu

@@ -1,0 +1,115 @@
+// Host-side analysis for the blocked sparse LU: ordering, symbolic fill,
+// diagonal block pointer (Algorithm 2), irregular blocking (Algorithm 3) and
+// the storage plan / task lists the device kernels walk.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "slu.h"
+
+namespace slu {
+
+// Storage plan of one block column ("level" i of Algorithm 1).
+//
+// Rows and columns of block i are [r0, r0 + b).  The diagonal block D_i is
+// dense b x b, column-major.  K_i lists the local columns of block i that
+// have an entry of S below the block; rows_i lists (sorted, global) the rows
+// below the block that have an entry of S in block column i.  Because S is
+// symmetric, the U blocks to the right of D_i couple the same index sets.
+//   P_i  (m x kappa, column-major, ld = m):  P_i[a, t]  = L(rows_i[a], r0 + K_i[t])
+//   Qt_i (m x kappa, column-major, ld = m):  Qt_i[a, t] = U(r0 + K_i[t], rows_i[a])
+// rows_i is cut into segments, one per target block row k > i.
+struct LevelDev {
+    int64_t offD, offP, offQ;   // slab offsets in doubles
+    int64_t Koff, Roff;         // offsets into K_idx / R_idx
+    int64_t task_begin, task_end;
+    int64_t tile_begin, tile_end;
+    int32_t r0, b, kappa, m;
+    int32_t chunk_begin, chunk_end;
+    int32_t seg_begin, seg_end;
+    int32_t lds_getrf;          // dynamic LDS bytes for GETRF
+    int32_t pad;
+};
+
+// One column chunk of the right-looking GETRF of D_i: local columns
+// [c0, c0 + w) and the local rows >= c0 + w of the block coupled to them.
+struct ChunkDev {
+    int32_t c0, w, nr, pad;
+    int64_t roff;               // offset into chunk_rows
+};
+
+// One SSSSM target (k, j) of level i:  B_kj -= P_i[a0:a0+alen, :] * Qt_i[b0:b0+blen, :]^T
+// The product element (a, b) lands at  tgt + rowmap[a]*rs + colmap[b]*cs
+// unless a map entry is -1 (the product is structurally zero there).
+struct TaskDev {
+    int64_t tgt;
+    int64_t rmap, cmap;         // offsets into maps
+    int32_t rs, cs;
+    int32_t a0, alen, b0, blen;
+};
+
+// Output tile of the SSSSM GEMM of a level.
+struct TileDev {
+    int32_t task;
+    int32_t tij;                // (ti << 16) | tj
+};
+
+struct Segment {
+    int32_t blk, start, len;
+};
+
+struct Analysis {
+    int64_t n = 0, nnz_a = 0;
+    slu_options opt{};
+    std::vector<int64_t> a_rowptr;
+    std::vector<int32_t> a_colidx;
+    std::vector<int32_t> perm, iperm;
+    std::vector<int64_t> s_colptr;   // lower CSC of S, diagonal first
+    std::vector<int32_t> s_rowidx;
+    std::vector<int64_t> blockptr;   // Algorithm 2, n + 1
+    std::vector<int64_t> bptr;       // block boundaries, p + 1
+    int64_t p = 0;
+    std::vector<int32_t> bid;        // block of every (permuted) row
+
+    std::vector<LevelDev> levels;
+    std::vector<int32_t> K_idx;      // local columns, concatenated per level
+    std::vector<int32_t> R_idx;      // global rows, concatenated per level
+    std::vector<Segment> segs;
+    std::vector<ChunkDev> chunks;
+    std::vector<int32_t> chunk_rows; // local rows
+    std::vector<TaskDev> tasks;
+    std::vector<int32_t> maps;
+    std::vector<TileDev> tiles;
+    std::vector<int64_t> slot;       // A entry (CSR order) -> slab position
+    std::vector<int32_t> posK;       // global column -> position in K of its block, or -1
+
+    int64_t slab_doubles = 0;
+    int64_t nonempty_blocks = 0;
+    double flops = 0.0;
+    double flops_getrf = 0.0, flops_panel = 0.0, flops_ssssm = 0.0;
+    double stored_flops = 0.0;
+    int32_t max_block = 0;
+    int32_t max_gemm_k = 0;
+};
+
+// Tile edge of the SSSSM output tiles.
+constexpr int kTile = 32;
+// Largest diagonal block factored in one LDS-resident chunk.
+constexpr int kLdsDenseMax = 128;
+// LDS budget of the chunked GETRF (bytes).
+constexpr int kGetrfLdsBudget = 150 * 1024;
+
+// Returns SLU_OK or an SLU_ERR_* code; fills *out.
+int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &opt,
+            Analysis *out);
+
+// Geometric nested dissection of an nx x ny x nz grid (new -> old).
+void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *perm);
+
+// Algorithm 3 with the exact-integer readings of the sampling.
+void irregular_blocking(const std::vector<int64_t> &blockptr, int sample_points, int step,
+                        int max_num, int advance, std::vector<int64_t> *ptr);
+
+}  // namespace slu

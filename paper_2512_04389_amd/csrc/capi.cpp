@@ -1,0 +1,473 @@
+// C ABI of the blocked sparse LU (declared in include/slu.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "analyze.hpp"
+#include "kernels.hpp"
+#include "slu.h"
+
+struct slu_handle {
+    slu::Analysis an;
+    size_t ws_bytes = 0;
+    void *ws = nullptr;
+    slu::DevPlan dev{};
+    // byte offsets of the workspace regions
+    size_t o_slab, o_levels, o_K, o_R, o_chunks, o_crows, o_tasks, o_maps, o_tiles, o_slot, o_arow, o_acol,
+        o_atcol, o_atrow, o_atv, o_perm, o_info, o_scratch, o_norms;
+    std::vector<int64_t> at_colptr;
+    std::vector<int32_t> at_rowidx;
+    std::vector<int64_t> at_vidx;
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;          // event pool for per-kernel timing
+    std::vector<int> ev_kind;            // kernel class of each recorded pair
+    double kern_ms[SLU_NUM_KERNELS] = {0, 0, 0, 0};
+    int64_t kern_n[SLU_NUM_KERNELS] = {0, 0, 0, 0};
+    bool bound = false;
+    bool factored = false;
+    int64_t zero_pivot_col = -1;
+    int solve_cols = slu::kSolveCols;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void plan_workspace(slu_handle *h) {
+    const slu::Analysis &an = h->an;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    h->o_slab = take((size_t)an.slab_doubles * 8);
+    h->o_levels = take(an.levels.size() * sizeof(slu::LevelDev));
+    h->o_K = take(an.K_idx.size() * 4);
+    h->o_R = take(an.R_idx.size() * 4);
+    h->o_chunks = take(an.chunks.size() * sizeof(slu::ChunkDev));
+    h->o_crows = take(an.chunk_rows.size() * 4);
+    h->o_tasks = take(an.tasks.size() * sizeof(slu::TaskDev));
+    h->o_maps = take(an.maps.size() * 4);
+    h->o_tiles = take(an.tiles.size() * sizeof(slu::TileDev));
+    h->o_slot = take(an.slot.size() * 8);
+    h->o_arow = take(an.a_rowptr.size() * 8);
+    h->o_acol = take(an.a_colidx.size() * 4);
+    h->o_atcol = take(h->at_colptr.size() * 8);
+    h->o_atrow = take(h->at_rowidx.size() * 4);
+    h->o_atv = take(h->at_vidx.size() * 8);
+    h->o_perm = take(an.perm.size() * 4);
+    h->o_info = take(64);
+    h->o_scratch = take((size_t)an.n * slu::kSolveCols * 8);
+    h->o_norms = take(64 * 8);
+    h->ws_bytes = o;
+}
+
+void build_transpose(slu_handle *h) {
+    const slu::Analysis &an = h->an;
+    const int64_t n = an.n, nnz = an.nnz_a;
+    h->at_colptr.assign(n + 1, 0);
+    for (int64_t q = 0; q < nnz; ++q) h->at_colptr[an.a_colidx[q] + 1] += 1;
+    for (int64_t j = 0; j < n; ++j) h->at_colptr[j + 1] += h->at_colptr[j];
+    h->at_rowidx.assign(nnz, 0);
+    h->at_vidx.assign(nnz, 0);
+    std::vector<int64_t> fill(h->at_colptr.begin(), h->at_colptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = an.a_rowptr[i]; q < an.a_rowptr[i + 1]; ++q) {
+            const int64_t at = fill[an.a_colidx[q]]++;
+            h->at_rowidx[at] = (int32_t)i;
+            h->at_vidx[at] = q;
+        }
+}
+
+template <class T>
+hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync((char *)base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, int trans, hipStream_t s) {
+    if (!h || (!B && nrhs > 0) || (!X && nrhs > 0) || nrhs < 0) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    if (!h->factored) return SLU_ERR_NOT_FACTORED;
+    const slu::Analysis &an = h->an;
+    if (ld < an.n || ld < 1) return SLU_ERR_ARG;
+    const slu::DevPlan &d = h->dev;
+    const int p = (int)an.p;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += h->solve_cols) {
+        const int nc = (int)std::min<int64_t>(h->solve_cols, nrhs - c0);
+        hipError_t e = slu::launch_gather_perm(d, B + c0 * ld, ld, nc, s);
+        if (e != hipSuccess) return SLU_ERR_HIP;
+        for (int i = 0; i < p; ++i) {
+            const slu::LevelDev &L = an.levels[i];
+            if (slu::launch_fwd_diag(d, i, L.b, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+            if (slu::launch_fwd_update(d, i, L.m, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+        }
+        for (int i = p - 1; i >= 0; --i) {
+            const slu::LevelDev &L = an.levels[i];
+            if (slu::launch_bwd_update(d, i, L.kappa, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+            if (slu::launch_bwd_diag(d, i, L.b, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+        }
+        e = slu::launch_scatter_perm(d, X + c0 * ld, ld, nc, s);
+        if (e != hipSuccess) return SLU_ERR_HIP;
+    }
+    return SLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void slu_default_options(slu_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->sample_points = 1000;
+    opt->step = 2;
+    opt->max_num = 3;
+    opt->advance = 1;
+    opt->blocking = SLU_BLOCK_IRREGULAR;
+    opt->regular_block = 0;
+    opt->ordering = SLU_ORDER_NATURAL;
+    opt->user_perm = nullptr;
+}
+
+int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options *opt,
+                slu_handle **out) {
+    if (!out) return SLU_ERR_ARG;
+    *out = nullptr;
+    slu_options o;
+    if (opt)
+        o = *opt;
+    else
+        slu_default_options(&o);
+    slu_handle *h = new (std::nothrow) slu_handle();
+    if (!h) return SLU_ERR_NOMEM;
+    int rc;
+    try {
+        rc = slu::analyze(n, rowptr, colidx, o, &h->an);
+        if (rc == SLU_OK) {
+            build_transpose(h);
+            // the diagonal sweeps of the solve hold b x nc doubles in LDS
+            const int64_t mb = std::max<int32_t>(h->an.max_block, 1);
+            h->solve_cols = (int)std::min<int64_t>(slu::kSolveCols, (150 * 1024) / (8 * mb));
+            for (const slu::LevelDev &L : h->an.levels)
+                if (L.lds_getrf > 160 * 1024) rc = SLU_ERR_LIMIT;
+            if (h->solve_cols < 1) rc = SLU_ERR_LIMIT;
+            plan_workspace(h);
+        }
+    } catch (const std::bad_alloc &) {
+        rc = SLU_ERR_NOMEM;
+    }
+    if (rc != SLU_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SLU_OK;
+}
+
+int slu_workspace_size(const slu_handle *h, size_t *bytes) {
+    if (!h || !bytes) return SLU_ERR_ARG;
+    *bytes = h->ws_bytes;
+    return SLU_OK;
+}
+
+int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stream) {
+    if (!h || !device_ptr) return SLU_ERR_ARG;
+    if (bytes < h->ws_bytes || ((uintptr_t)device_ptr & 255) != 0) return SLU_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (slu::setup_kernel_attributes() != hipSuccess) return SLU_ERR_HIP;
+    char *base = (char *)device_ptr;
+    const slu::Analysis &an = h->an;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(base, h->o_levels, an.levels, s);
+    if (e == hipSuccess) e = upload(base, h->o_K, an.K_idx, s);
+    if (e == hipSuccess) e = upload(base, h->o_R, an.R_idx, s);
+    if (e == hipSuccess) e = upload(base, h->o_chunks, an.chunks, s);
+    if (e == hipSuccess) e = upload(base, h->o_crows, an.chunk_rows, s);
+    if (e == hipSuccess) e = upload(base, h->o_tasks, an.tasks, s);
+    if (e == hipSuccess) e = upload(base, h->o_maps, an.maps, s);
+    if (e == hipSuccess) e = upload(base, h->o_tiles, an.tiles, s);
+    if (e == hipSuccess) e = upload(base, h->o_slot, an.slot, s);
+    if (e == hipSuccess) e = upload(base, h->o_arow, an.a_rowptr, s);
+    if (e == hipSuccess) e = upload(base, h->o_acol, an.a_colidx, s);
+    if (e == hipSuccess) e = upload(base, h->o_atcol, h->at_colptr, s);
+    if (e == hipSuccess) e = upload(base, h->o_atrow, h->at_rowidx, s);
+    if (e == hipSuccess) e = upload(base, h->o_atv, h->at_vidx, s);
+    if (e == hipSuccess) e = upload(base, h->o_perm, an.perm, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return SLU_ERR_HIP;
+    slu::DevPlan &d = h->dev;
+    d.slab = (double *)(base + h->o_slab);
+    d.levels = (const slu::LevelDev *)(base + h->o_levels);
+    d.K_idx = (const int32_t *)(base + h->o_K);
+    d.R_idx = (const int32_t *)(base + h->o_R);
+    d.chunks = (const slu::ChunkDev *)(base + h->o_chunks);
+    d.chunk_rows = (const int32_t *)(base + h->o_crows);
+    d.tasks = (const slu::TaskDev *)(base + h->o_tasks);
+    d.maps = (const int32_t *)(base + h->o_maps);
+    d.tiles = (const slu::TileDev *)(base + h->o_tiles);
+    d.slot = (const int64_t *)(base + h->o_slot);
+    d.a_rowptr = (const int64_t *)(base + h->o_arow);
+    d.a_colidx = (const int32_t *)(base + h->o_acol);
+    d.at_colptr = (const int64_t *)(base + h->o_atcol);
+    d.at_rowidx = (const int32_t *)(base + h->o_atrow);
+    d.at_vidx = (const int64_t *)(base + h->o_atv);
+    d.perm = (const int32_t *)(base + h->o_perm);
+    d.info = (unsigned long long *)(base + h->o_info);
+    d.scratch = (double *)(base + h->o_scratch);
+    d.norms = (unsigned long long *)(base + h->o_norms);
+    d.n = an.n;
+    d.nnz_a = an.nnz_a;
+    d.slab_doubles = an.slab_doubles;
+    h->ws = device_ptr;
+    h->bound = true;
+    h->factored = false;
+    return SLU_OK;
+}
+
+namespace {
+// Per-kernel timing: an event pair around a launch when profiling is on.
+struct KernelTimer {
+    slu_handle *h;
+    hipStream_t s;
+    size_t used = 0;
+    hipError_t begin(int kind) {
+        if (!h->profiling) return hipSuccess;
+        if (used + 2 > h->ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                h->ev.push_back(e);
+            }
+        }
+        if (h->ev_kind.size() < h->ev.size() / 2) h->ev_kind.resize(h->ev.size() / 2);
+        h->ev_kind[used / 2] = kind;
+        return hipEventRecord(h->ev[used], s);
+    }
+    hipError_t end() {
+        if (!h->profiling) return hipSuccess;
+        hipError_t e = hipEventRecord(h->ev[used + 1], s);
+        used += 2;
+        return e;
+    }
+    hipError_t collect() {
+        for (int k = 0; k < SLU_NUM_KERNELS; ++k) {
+            h->kern_ms[k] = 0.0;
+            h->kern_n[k] = 0;
+        }
+        if (!h->profiling) return hipSuccess;
+        for (size_t q = 0; q < used; q += 2) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]);
+            if (e != hipSuccess) return e;
+            h->kern_ms[h->ev_kind[q / 2]] += ms;
+            h->kern_n[h->ev_kind[q / 2]] += 1;
+        }
+        return hipSuccess;
+    }
+};
+}  // namespace
+
+int slu_factor(slu_handle *h, const double *values, void *stream) {
+    if (!h || (!values && h->an.nnz_a > 0)) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    const slu::Analysis &an = h->an;
+    const slu::DevPlan &d = h->dev;
+    h->factored = false;
+    h->zero_pivot_col = -1;
+    KernelTimer kt{h, s};
+#define SLU_TIMED(kind, call)                                              \
+    do {                                                                   \
+        if (kt.begin(kind) != hipSuccess) return SLU_ERR_HIP;              \
+        if ((call) != hipSuccess) return SLU_ERR_HIP;                      \
+        if (kt.end() != hipSuccess) return SLU_ERR_HIP;                    \
+    } while (0)
+    if (slu::launch_info_reset(d, s) != hipSuccess) return SLU_ERR_HIP;
+    SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_zero(d.slab, an.slab_doubles, s));
+    SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_scatter(d, values, s));
+    for (int64_t i = 0; i < an.p; ++i) {
+        const slu::LevelDev &L = an.levels[i];
+        SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf(d, (int)i, L.lds_getrf, s));
+        if (L.kappa > 0) {
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_trsm_panels(d, (int)i, L.m, L.kappa, s));
+            SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, (int)i, L.tile_end - L.tile_begin, s));
+        }
+    }
+#undef SLU_TIMED
+    unsigned long long flag = 0;
+    if (hipMemcpyAsync(&flag, d.info, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess) return SLU_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
+    if (kt.collect() != hipSuccess) return SLU_ERR_HIP;
+    if (flag != ~0ull) {
+        h->zero_pivot_col = (int64_t)flag;
+        return SLU_ZERO_PIVOT;
+    }
+    h->factored = true;
+    return SLU_OK;
+}
+
+int slu_solve(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, void *stream) {
+    return solve_impl(h, B, X, nrhs, ld, 0, (hipStream_t)stream);
+}
+
+int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, void *stream) {
+    return solve_impl(h, B, X, nrhs, ld, 1, (hipStream_t)stream);
+}
+
+int slu_backward_error(slu_handle *h, const double *values, const double *B, const double *X, int64_t nrhs,
+                       int64_t ld, int transpose, double *eta, void *stream) {
+    if (!h || !eta || nrhs < 0 || (nrhs > 0 && (!B || !X || !values))) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += slu::kSolveCols) {
+        const int nc = (int)std::min<int64_t>(slu::kSolveCols, nrhs - c0);
+        if (slu::launch_residual_norms(h->dev, values, B + c0 * ld, X + c0 * ld, ld, nc, transpose ? 1 : 0, s) !=
+            hipSuccess)
+            return SLU_ERR_HIP;
+        unsigned long long nb[64];
+        if (hipMemcpyAsync(nb, h->dev.norms, sizeof(nb), hipMemcpyDeviceToHost, s) != hipSuccess) return SLU_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
+        double v[64];
+        std::memcpy(v, nb, sizeof(v));
+        for (int c = 0; c < nc; ++c) {
+            const double den = v[48] * v[16 + c] + v[32 + c];
+            eta[c0 + c] = den > 0.0 ? v[c] / den : (v[c] > 0.0 ? 1.0 / 0.0 : 0.0);
+        }
+    }
+    return SLU_OK;
+}
+
+int slu_get_info(const slu_handle *h, slu_info *info) {
+    if (!h || !info) return SLU_ERR_ARG;
+    const slu::Analysis &an = h->an;
+    std::memset(info, 0, sizeof(*info));
+    info->n = an.n;
+    info->nnz_a = an.nnz_a;
+    info->nnz_s = 2 * (an.s_colptr.empty() ? 0 : an.s_colptr[an.n]) - an.n;
+    info->nblocks = an.p;
+    info->nonempty_blocks = an.nonempty_blocks;
+    info->ssssm_tasks = (int64_t)an.tasks.size();
+    info->flops = an.flops;
+    info->flops_getrf = an.flops_getrf;
+    info->flops_panel = an.flops_panel;
+    info->flops_ssssm = an.flops_ssssm;
+    info->stored_flops = an.stored_flops;
+    info->slab_bytes = an.slab_doubles * 8;
+    info->workspace_bytes = (int64_t)h->ws_bytes;
+    info->zero_pivot_col = h->zero_pivot_col;
+    info->factored = h->factored ? 1 : 0;
+    info->max_block = an.max_block;
+    return SLU_OK;
+}
+
+int slu_get_perm(const slu_handle *h, int32_t *perm) {
+    if (!h || (!perm && h->an.n > 0)) return SLU_ERR_ARG;
+    std::copy(h->an.perm.begin(), h->an.perm.end(), perm);
+    return SLU_OK;
+}
+
+int slu_get_blockptr(const slu_handle *h, int64_t *blockptr) {
+    if (!h || !blockptr) return SLU_ERR_ARG;
+    std::copy(h->an.blockptr.begin(), h->an.blockptr.end(), blockptr);
+    return SLU_OK;
+}
+
+int slu_get_blocking(const slu_handle *h, int64_t *ptr) {
+    if (!h || !ptr) return SLU_ERR_ARG;
+    std::copy(h->an.bptr.begin(), h->an.bptr.end(), ptr);
+    return SLU_OK;
+}
+
+int slu_get_pattern(const slu_handle *h, int64_t *colptr, int32_t *rowidx) {
+    if (!h || !colptr || (!rowidx && !h->an.s_rowidx.empty())) return SLU_ERR_ARG;
+    std::copy(h->an.s_colptr.begin(), h->an.s_colptr.end(), colptr);
+    std::copy(h->an.s_rowidx.begin(), h->an.s_rowidx.end(), rowidx);
+    return SLU_OK;
+}
+
+int slu_get_factors(const slu_handle *h, double *lval, double *uval, void *stream) {
+    if (!h || !lval || !uval) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    if (!h->factored) return SLU_ERR_NOT_FACTORED;
+    const slu::Analysis &an = h->an;
+    std::vector<double> slab;
+    try {
+        slab.resize((size_t)an.slab_doubles);
+    } catch (const std::bad_alloc &) {
+        return SLU_ERR_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!slab.empty() &&
+        hipMemcpyAsync(slab.data(), h->dev.slab, slab.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SLU_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
+    for (int64_t c = 0; c < an.n; ++c) {
+        const int32_t J = an.bid[c];
+        const slu::LevelDev &LJ = an.levels[J];
+        for (int64_t q = an.s_colptr[c]; q < an.s_colptr[c + 1]; ++q) {
+            const int32_t r = an.s_rowidx[q];
+            const int32_t I = an.bid[r];
+            if (I == J) {
+                const int64_t lr = r - LJ.r0, lc = c - LJ.r0;
+                lval[q] = slab[LJ.offD + lr + lc * LJ.b];
+                uval[q] = slab[LJ.offD + lc + lr * LJ.b];
+            } else {
+                const int32_t *rows = an.R_idx.data() + LJ.Roff;
+                const int64_t rp = std::lower_bound(rows, rows + LJ.m, r) - rows;
+                const int64_t kp = an.posK[c];
+                lval[q] = slab[LJ.offP + rp + kp * LJ.m];
+                uval[q] = slab[LJ.offQ + rp + kp * LJ.m];
+            }
+        }
+    }
+    return SLU_OK;
+}
+
+const char *slu_error_string(int code) {
+    switch (code) {
+        case SLU_OK: return "success";
+        case SLU_ZERO_PIVOT: return "zero or non-finite pivot";
+        case SLU_ERR_ARG: return "invalid argument";
+        case SLU_ERR_ROWPTR: return "rowptr does not start at 0 or is not monotone";
+        case SLU_ERR_COLIDX: return "column index out of range";
+        case SLU_ERR_UNSORTED: return "column indices of a row unsorted or duplicated";
+        case SLU_ERR_PERM: return "user ordering is not a permutation";
+        case SLU_ERR_STATE: return "call out of order (bind a workspace first)";
+        case SLU_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+        case SLU_ERR_HIP: return "HIP runtime error";
+        case SLU_ERR_NOMEM: return "host allocation failed";
+        case SLU_ERR_NOT_FACTORED: return "no successful factorization";
+        case SLU_ERR_LIMIT: return "problem exceeds the library's size limits";
+        default: return "unknown error code";
+    }
+}
+
+int slu_set_profiling(slu_handle *h, int enable) {
+    if (!h) return SLU_ERR_ARG;
+    h->profiling = enable != 0;
+    return SLU_OK;
+}
+
+int slu_get_kernel_times(const slu_handle *h, double *ms, int64_t *launches) {
+    if (!h || !ms || !launches) return SLU_ERR_ARG;
+    for (int k = 0; k < SLU_NUM_KERNELS; ++k) {
+        ms[k] = h->kern_ms[k];
+        launches[k] = h->kern_n[k];
+    }
+    return SLU_OK;
+}
+
+void slu_free(slu_handle *h) {
+    if (!h) return;
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+}
+
+}  // extern "C"

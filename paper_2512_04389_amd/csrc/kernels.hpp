@@ -1,0 +1,60 @@
+// Launch helpers for the gfx950 kernels of the blocked sparse LU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "analyze.hpp"
+
+namespace slu {
+
+// Device view of the uploaded structure (all pointers inside the workspace).
+struct DevPlan {
+    double *slab;
+    const LevelDev *levels;
+    const int32_t *K_idx;
+    const int32_t *R_idx;
+    const ChunkDev *chunks;
+    const int32_t *chunk_rows;
+    const TaskDev *tasks;
+    const int32_t *maps;
+    const TileDev *tiles;
+    const int64_t *slot;
+    const int64_t *a_rowptr;
+    const int32_t *a_colidx;
+    const int64_t *at_colptr;   // CSC of A: column pointers
+    const int32_t *at_rowidx;   // CSC of A: row of every entry
+    const int64_t *at_vidx;     // CSC of A: index of the entry in CSR order
+    const int32_t *perm;
+    unsigned long long *info;   // [0] smallest failed pivot column (or ~0)
+    double *scratch;            // n * kSolveCols doubles
+    unsigned long long *norms;  // 4 * kSolveCols (non-negative doubles as bits)
+    int64_t n, nnz_a, slab_doubles;
+};
+
+constexpr int kSolveCols = 16;
+
+hipError_t setup_kernel_attributes();
+
+hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
+hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);
+hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
+hipError_t launch_getrf(const DevPlan &d, int level, int lds_bytes, hipStream_t s);
+hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hipStream_t s);
+int trsm_rows_per_group(int kappa);
+hipError_t launch_ssssm(const DevPlan &d, int level, int64_t ntiles, hipStream_t s);
+
+// Solve pieces on the permuted work block W (n x nc, leading dimension n).
+hipError_t launch_gather_perm(const DevPlan &d, const double *B, int64_t ld, int nc, hipStream_t s);
+hipError_t launch_scatter_perm(const DevPlan &d, double *X, int64_t ld, int nc, hipStream_t s);
+hipError_t launch_fwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s);
+hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s);
+hipError_t launch_bwd_update(const DevPlan &d, int level, int kappa, int nc, int trans, hipStream_t s);
+hipError_t launch_bwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s);
+
+// Backward-error pieces: norms[0..nc) = ||r||, [16..) = ||x||, [32..) = ||b||, [48] = ||op(A)||.
+hipError_t launch_residual_norms(const DevPlan &d, const double *values, const double *B,
+                                 const double *X, int64_t ld, int nc, int trans, hipStream_t s);
+
+}  // namespace slu

@@ -1,0 +1,140 @@
+"""Host-side parity of slu_analyze with the oracle (no GPU needed).
+
+Ordering, filled pattern S, Algorithm 2 and Algorithm 3 must match the
+oracle bit for bit; malformed inputs must be rejected with the documented
+codes; the library must export every entry point of include/slu.h."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import blocking, ordering, symbolic
+
+slu = pytest.importorskip("paper_2512_04389_amd")
+from paper_2512_04389_amd import _abi  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_header_symbol():
+    hdr = open(os.path.join(ROOT, "include", "slu.h")).read()
+    names = set(re.findall(r"\b(slu_[a-z_]+)\s*\(", hdr))
+    assert names == set(_abi.EXPORTS)
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _structure_parity(n, rp, ci, dims, **kw):
+    h = slu.SparseLU(n, rp, ci, ordering="grid_nd", grid_dims=dims, **kw)
+    perm = ordering.nd_grid(dims)
+    assert np.array_equal(h.perm(), perm)
+    cp, ri = symbolic.symbolic(n, rp, ci, perm)
+    hcp, hri = h.pattern()
+    assert np.array_equal(hcp, cp) and np.array_equal(hri, ri)
+    bp = blocking.diag_block_ptr(n, cp, ri)
+    assert np.array_equal(h.blockptr(), bp)
+    if kw.get("blocking", "irregular") == "irregular":
+        ptr = blocking.irregular_blocking(bp, kw.get("sample_points", 1000), kw.get("step", 2),
+                                          kw.get("max_num", 3), kw.get("advance", 1))
+    else:
+        ptr = blocking.regular_blocking(n, kw["block_size"])
+    assert np.array_equal(h.blocking(), ptr)
+    info = h.info()
+    assert info["nnz_s"] == 2 * (int(cp[-1]) - n) + n
+    bi, bj, _ = blocking.nonempty_blocks(n, cp, ri, ptr)
+    assert info["nonempty_blocks"] == len(bi)
+    from oracle import metrics
+    assert info["flops"] == float(metrics.flops(cp))
+    return h
+
+
+@pytest.mark.parametrize("k", [8, 31, 64])
+def test_laplacian_2d(k):
+    n, rp, ci, _ = synth.laplacian_2d(k)
+    _structure_parity(n, rp, ci, (k, k, 1))
+
+
+@pytest.mark.parametrize("k", [5, 12, 16])
+def test_laplacian_3d(k):
+    n, rp, ci, _ = synth.laplacian_3d(k)
+    _structure_parity(n, rp, ci, (k, k, k))
+
+
+def test_regular_and_advance_options():
+    n, rp, ci, _ = synth.laplacian_3d(12)
+    _structure_parity(n, rp, ci, (12, 12, 12), blocking="regular", block_size=100)
+    _structure_parity(n, rp, ci, (12, 12, 12), advance=2)
+    _structure_parity(n, rp, ci, (12, 12, 12), sample_points=50, max_num=1)
+
+
+def test_rectangular_grids():
+    n, rp, ci, _ = synth.grid_laplacian((13, 7, 5))
+    _structure_parity(n, rp, ci, (13, 7, 5))
+    n, rp, ci, _ = synth.grid_laplacian((40, 3))
+    _structure_parity(n, rp, ci, (40, 3, 1))
+
+
+def test_user_perm_and_unsymmetric_pattern():
+    rng = np.random.default_rng(3)
+    n = 300
+    m = rng.random((n, n)) < 0.01
+    rows, cols = np.nonzero(m)
+    rp, ci, _ = synth.coo_to_csr(n, rows, cols)
+    perm = rng.permutation(n).astype(np.int32)
+    h = slu.SparseLU(n, rp, ci, ordering="user", perm=perm)
+    assert np.array_equal(h.perm(), perm)
+    cp, ri = symbolic.symbolic(n, rp, ci, perm)
+    hcp, hri = h.pattern()
+    assert np.array_equal(hcp, cp) and np.array_equal(hri, ri)
+    assert np.array_equal(h.blocking(), blocking.irregular_blocking(blocking.diag_block_ptr(n, cp, ri)))
+
+
+def test_bbd_small_natural():
+    n, rp, ci, _ = synth.bbd_circuit(n=3000, nblocks=6, border=60, border_nnz=3000, seed=2)
+    h = slu.SparseLU(n, rp, ci, ordering="natural")
+    cp, ri = symbolic.symbolic(n, rp, ci, np.arange(n, dtype=np.int32))
+    hcp, hri = h.pattern()
+    assert np.array_equal(hcp, cp) and np.array_equal(hri, ri)
+
+
+def _code(n, rp, ci, **kw):
+    with pytest.raises(_abi.SluError) as e:
+        slu.SparseLU(n, np.asarray(rp), np.asarray(ci), **kw)
+    return e.value.code
+
+
+def test_error_codes():
+    assert _code(2, [1, 1, 2], [0, 1]) == _abi.SLU_ERR_ROWPTR
+    assert _code(2, [0, 2, 1], [0, 1]) == _abi.SLU_ERR_ROWPTR
+    assert _code(2, [0, 1, 2], [0, 2]) == _abi.SLU_ERR_COLIDX
+    assert _code(2, [0, 1, 2], [0, -1]) == _abi.SLU_ERR_COLIDX
+    assert _code(2, [0, 2, 2], [1, 0]) == _abi.SLU_ERR_UNSORTED
+    assert _code(2, [0, 2, 2], [1, 1]) == _abi.SLU_ERR_UNSORTED
+    assert _code(2, [0, 1, 2], [0, 1], ordering="user", perm=[0, 0]) == _abi.SLU_ERR_PERM
+    assert _code(2, [0, 1, 2], [0, 1], ordering="grid_nd", grid_dims=(3, 1, 1)) == _abi.SLU_ERR_ARG
+    assert _code(2, [0, 1, 2], [0, 1], blocking="regular", block_size=0) == _abi.SLU_ERR_ARG
+    assert _code(-1, [0], []) == _abi.SLU_ERR_ARG
+
+
+def test_degenerate_sizes():
+    h = slu.SparseLU(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert h.info()["nblocks"] == 0 and h.blocking().tolist() == [0]
+    h = slu.SparseLU(1, np.array([0, 1]), np.array([0]))
+    assert h.blocking().tolist() == [0, 1]
+    # missing diagonal entries still enter S
+    h = slu.SparseLU(3, np.array([0, 1, 1, 2]), np.array([2, 0]))
+    cp, ri = h.pattern()
+    assert all(ri[cp[k]] == k for k in range(3))
+
+
+def test_device_calls_need_workspace():
+    n, rp, ci, _ = synth.laplacian_2d(4)
+    h = slu.SparseLU(n, rp, ci)
+    assert h.workspace_size() > 0
+    assert _abi.lib.slu_factor(h._h, ctypes.c_void_p(8), ctypes.c_void_p(0)) == _abi.SLU_ERR_STATE
+    assert _abi.lib.slu_solve(h._h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, n,
+                              ctypes.c_void_p(0)) == _abi.SLU_ERR_STATE

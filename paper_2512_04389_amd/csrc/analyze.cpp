@@ -396,6 +396,45 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         L.chunk_end = (int32_t)an.chunks.size();
     }
 
+    // compact coupled triangles for the panel solves: sizes and the
+    // structurally nonzero 16 x 16 tiles of U_ii[K_i, K_i]
+    {
+        int64_t toff = 0;
+        std::vector<int64_t> keys;
+        for (int64_t i = 0; i < p; ++i) {
+            LevelDev &L = an.levels[i];
+            const int32_t kp = (L.kappa + 15) / 16 * 16;
+            const int32_t nt = kp / 16;
+            L.kp = kp;
+            L.offT = toff;
+            toff += align32(2 * (int64_t)kp * kp + 2 * (int64_t)nt * 256);
+            L.trow = (int32_t)an.trow_ptr.size();
+            keys.clear();
+            const int64_t r0 = L.r0, r1 = (int64_t)L.r0 + L.b;
+            for (int64_t c = r0; c < r1; ++c) {
+                const int32_t tc = an.posK[c];
+                if (tc < 0) continue;
+                for (int64_t q = an.s_colptr[c] + 1; q < an.s_colptr[c + 1]; ++q) {
+                    const int32_t r = an.s_rowidx[q];
+                    if (r >= r1) break;
+                    const int32_t tr = an.posK[r];
+                    if (tr < 0) continue;
+                    // U(c, r) with c < r: tile (tc / 16, tr / 16) of the upper triangle
+                    if (tr / 16 != tc / 16) keys.push_back((int64_t)(tc / 16) * nt + tr / 16);
+                }
+            }
+            std::sort(keys.begin(), keys.end());
+            keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+            size_t q = 0;
+            for (int32_t row = 0; row < nt; ++row) {
+                an.trow_ptr.push_back((int32_t)an.trow_idx.size());
+                while (q < keys.size() && keys[q] / nt == row) an.trow_idx.push_back((int32_t)(keys[q++] % nt));
+            }
+            an.trow_ptr.push_back((int32_t)an.trow_idx.size());
+        }
+        an.tri_doubles = toff;
+    }
+
     // SSSSM tasks, maps and tiles
     for (int64_t i = 0; i < p; ++i) {
         LevelDev &L = an.levels[i];

@@ -21,8 +21,17 @@ namespace slu {
 //   P_i  (m x kappa, column-major, ld = m):  P_i[a, t]  = L(rows_i[a], r0 + K_i[t])
 //   Qt_i (m x kappa, column-major, ld = m):  Qt_i[a, t] = U(r0 + K_i[t], rows_i[a])
 // rows_i is cut into segments, one per target block row k > i.
+//
+// The panel solves use compact copies of the coupled triangles in the "tri"
+// region at offT (kp = kappa rounded up to 16, nt = kp / 16):
+//   Tu  (kp x kp, row-major) = U_ii[K_i, K_i]      upper, identity padding
+//   Tl  (kp x kp, row-major) = L_ii[K_i, K_i]^T    unit upper
+//   then nt inverted 16 x 16 diagonal tiles of Tu, then nt of Tl.
+// trow_ptr[trow + c] .. trow_ptr[trow + c + 1] list the tile columns c' > c
+// with a structurally nonzero tile (c, c') of Tu (and so of Tl).
 struct LevelDev {
     int64_t offD, offP, offQ;   // slab offsets in doubles
+    int64_t offT;               // tri region offset in doubles
     int64_t Koff, Roff;         // offsets into K_idx / R_idx
     int64_t task_begin, task_end;
     int64_t tile_begin, tile_end;
@@ -30,6 +39,8 @@ struct LevelDev {
     int32_t chunk_begin, chunk_end;
     int32_t seg_begin, seg_end;
     int32_t lds_getrf;          // dynamic LDS bytes for GETRF
+    int32_t kp;                 // kappa rounded up to a multiple of 16
+    int32_t trow;               // offset into trow_ptr
     int32_t pad;
 };
 
@@ -82,6 +93,9 @@ struct Analysis {
     std::vector<TaskDev> tasks;
     std::vector<int32_t> maps;
     std::vector<TileDev> tiles;
+    std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
+    std::vector<int32_t> trow_idx;
+    int64_t tri_doubles = 0;
     std::vector<int64_t> slot;       // A entry (CSR order) -> slab position
     std::vector<int32_t> posK;       // global column -> position in K of its block, or -1
 

@@ -16,7 +16,7 @@ struct slu_handle {
     void *ws = nullptr;
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
-    size_t o_slab, o_levels, o_K, o_R, o_chunks, o_crows, o_tasks, o_maps, o_tiles, o_slot, o_arow, o_acol,
+    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_tasks, o_maps, o_tiles, o_slot, o_arow, o_acol,
         o_atcol, o_atrow, o_atv, o_perm, o_info, o_scratch, o_norms;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
@@ -45,6 +45,9 @@ void plan_workspace(slu_handle *h) {
         return at;
     };
     h->o_slab = take((size_t)an.slab_doubles * 8);
+    h->o_tri = take((size_t)an.tri_doubles * 8);
+    h->o_trow_ptr = take(an.trow_ptr.size() * 4);
+    h->o_trow_idx = take(an.trow_idx.size() * 4);
     h->o_levels = take(an.levels.size() * sizeof(slu::LevelDev));
     h->o_K = take(an.K_idx.size() * 4);
     h->o_R = take(an.R_idx.size() * 4);
@@ -184,6 +187,8 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     const slu::Analysis &an = h->an;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(base, h->o_levels, an.levels, s);
+    if (e == hipSuccess) e = upload(base, h->o_trow_ptr, an.trow_ptr, s);
+    if (e == hipSuccess) e = upload(base, h->o_trow_idx, an.trow_idx, s);
     if (e == hipSuccess) e = upload(base, h->o_K, an.K_idx, s);
     if (e == hipSuccess) e = upload(base, h->o_R, an.R_idx, s);
     if (e == hipSuccess) e = upload(base, h->o_chunks, an.chunks, s);
@@ -202,6 +207,9 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e != hipSuccess) return SLU_ERR_HIP;
     slu::DevPlan &d = h->dev;
     d.slab = (double *)(base + h->o_slab);
+    d.tri = (double *)(base + h->o_tri);
+    d.trow_ptr = (const int32_t *)(base + h->o_trow_ptr);
+    d.trow_idx = (const int32_t *)(base + h->o_trow_idx);
     d.levels = (const slu::LevelDev *)(base + h->o_levels);
     d.K_idx = (const int32_t *)(base + h->o_K);
     d.R_idx = (const int32_t *)(base + h->o_R);
@@ -293,9 +301,13 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
     SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_scatter(d, values, s));
     for (int64_t i = 0; i < an.p; ++i) {
         const slu::LevelDev &L = an.levels[i];
-        SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf(d, (int)i, L.lds_getrf, s));
+        if (L.b <= slu::kLdsDenseMax)
+            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_dense(d, (int)i, L.b, s));
+        else
+            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf(d, (int)i, L.lds_getrf, s));
         if (L.kappa > 0) {
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_trsm_panels(d, (int)i, L.m, L.kappa, s));
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather(d, (int)i, L.kp, s));
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve(d, (int)i, L.m, L.kp, s));
             SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, (int)i, L.tile_end - L.tile_begin, s));
         }
     }

@@ -225,6 +225,285 @@ hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hip
     return hipGetLastError();
 }
 
+// ------------------------------------------------- dense GETRF (b <= 128)
+// Diagonal blocks of at most 128 rows: the whole block in LDS, blocked
+// right-looking LU with 16-column panels.  One wave factors the panel in
+// registers (each lane owns up to two rows; pivot row values are broadcast
+// with lane shuffles), all threads solve the panel's U rows, and the four
+// waves apply the trailing update as 16 x 16 FP64 MFMA tiles.
+__global__ __launch_bounds__(256) void k_getrf_dense(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                     int level, unsigned long long *__restrict__ info) {
+    extern __shared__ double ds[];
+    const LevelDev L = levels[level];
+    double *__restrict__ D = slab + L.offD;
+    const int b = L.b;
+    const int ldd = b | 1;                 // odd stride: conflict-free column-strided LDS access
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int c = 0; c < b; ++c)
+        for (int r = tid; r < b; r += 256) ds[c * ldd + r] = D[r + (size_t)c * b];
+    __syncthreads();
+    for (int c0 = 0; c0 < b; c0 += 16) {
+        const int cw = min(16, b - c0);
+        if (wave == 0) {
+            const int r0 = c0 + lane, r1 = c0 + 64 + lane;
+            const bool v0ok = r0 < b, v1ok = r1 < b;
+            double v0[16], v1[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                v0[j] = (j < cw && v0ok) ? ds[(c0 + j) * ldd + r0] : 0.0;
+                v1[j] = (j < cw && v1ok) ? ds[(c0 + j) * ldd + r1] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < cw) {
+                    const double piv = __shfl(v0[k], k, 64);
+                    if (lane == 0 && !(piv != 0.0 && isfinite(piv)))
+                        atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
+                    if (lane > k) v0[k] = v0[k] / piv;
+                    v1[k] = v1[k] / piv;
+                    const double l0 = v0[k], l1 = v1[k];
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        const double u = __shfl(v0[j], k, 64);
+                        if (lane > k) v0[j] -= l0 * u;
+                        v1[j] -= l1 * u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < cw && v0ok) ds[(c0 + j) * ldd + r0] = v0[j];
+                if (j < cw && v1ok) ds[(c0 + j) * ldd + r1] = v1[j];
+            }
+        }
+        __syncthreads();
+        for (int col = c0 + cw + tid; col < b; col += 256) {
+            double u[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) u[j] = j < cw ? ds[col * ldd + c0 + j] : 0.0;
+#pragma unroll
+            for (int j = 1; j < 16; ++j) {
+                double v = u[j];
+#pragma unroll
+                for (int jp = 0; jp < j; ++jp) v -= ds[(c0 + jp) * ldd + c0 + j] * u[jp];
+                u[j] = v;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < cw) ds[col * ldd + c0 + j] = u[j];
+        }
+        __syncthreads();
+        const int t0 = c0 + cw;
+        const int nrem = b - t0;
+        const int ntl = (nrem + 15) >> 4;
+        for (int t = wave; t < ntl * ntl; t += 4) {
+            const int ti = t / ntl, tj = t - ti * ntl;
+            const int row0 = t0 + 16 * ti, col0 = t0 + 16 * tj;
+            const int ccol = col0 + li;
+            double4_t acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + lk + 4 * r;
+                acc[r] = (row < b && ccol < b) ? ds[ccol * ldd + row] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const double a = (k < cw && row0 + li < b) ? -ds[(c0 + k) * ldd + row0 + li] : 0.0;
+                const double bv = (k < cw && ccol < b) ? ds[ccol * ldd + c0 + k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + lk + 4 * r;
+                if (row < b && ccol < b) ds[ccol * ldd + row] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    for (int c = 0; c < b; ++c)
+        for (int r = tid; r < b; r += 256) D[r + (size_t)c * b] = ds[c * ldd + r];
+}
+
+hipError_t launch_getrf_dense(const DevPlan &d, int level, int b, hipStream_t s) {
+    const size_t lds = (size_t)b * (b | 1) * sizeof(double);
+    hipLaunchKernelGGL(k_getrf_dense, dim3(1), dim3(256), lds, s, d.slab, d.levels, level, d.info);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- compact coupled triangles
+// One workgroup per tile row tr of the compact triangles (see LevelDev):
+// copies rows [16 tr, 16 tr + 16) of Tu = U_ii[K, K] and Tl = L_ii[K, K]^T
+// from the factored diagonal block, then inverts the two diagonal tiles
+// (back substitution per column, FP64 divisions by the pivots).
+__global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ slab, double *__restrict__ tri,
+                                                    const LevelDev *__restrict__ levels, int level,
+                                                    const int32_t *__restrict__ Kidx) {
+    __shared__ double du[16][17], dl[16][17];
+    const LevelDev L = levels[level];
+    const int kp = L.kp, kap = L.kappa, b = L.b, nt = kp >> 4;
+    const int tr = blockIdx.x;
+    const double *__restrict__ D = slab + L.offD;
+    const int32_t *__restrict__ K = Kidx + L.Koff;
+    double *__restrict__ Tu = tri + L.offT;
+    double *__restrict__ Tl = Tu + (size_t)kp * kp;
+    double *__restrict__ Iu = Tl + (size_t)kp * kp;
+    double *__restrict__ Il = Iu + (size_t)nt * 256;
+    const int width = kp - 16 * tr;
+    for (int e = threadIdx.x; e < 16 * width; e += 256) {
+        const int rr = e / width, cc = e - rr * width;
+        const int t1 = 16 * tr + rr, t2 = 16 * tr + cc;
+        double u, lt;
+        if (t1 < kap && t2 < kap) {
+            const size_t k1 = (size_t)K[t1], k2 = (size_t)K[t2];
+            u = t1 <= t2 ? D[k1 + k2 * b] : 0.0;
+            lt = t1 < t2 ? D[k2 + k1 * b] : (t1 == t2 ? 1.0 : 0.0);
+        } else {
+            u = t1 == t2 ? 1.0 : 0.0;
+            lt = u;
+        }
+        Tu[(size_t)t1 * kp + t2] = u;
+        Tl[(size_t)t1 * kp + t2] = lt;
+        if (cc < 16) {
+            du[rr][cc] = u;
+            dl[rr][cc] = lt;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int j = threadIdx.x & 15;
+        const bool upper = threadIdx.x < 16;
+        double x[16];
+#pragma unroll
+        for (int r = 15; r >= 0; --r) {
+            double v = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = r + 1; q < 16; ++q) v -= (upper ? du[r][q] : dl[r][q]) * x[q];
+            x[r] = upper ? v / du[r][r] : v;
+        }
+        double *out = (upper ? Iu : Il) + (size_t)tr * 256;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[r * 16 + j] = x[r];
+    }
+}
+
+hipError_t launch_tri_gather(const DevPlan &d, int level, int kp, hipStream_t s) {
+    if (kp <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)(kp / 16)), dim3(256), 0, s, d.slab, d.tri, d.levels, level,
+                       d.K_idx);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ panel solves (v2)
+// Alg. 1 "B_ij <- L_ii^{-1} B_ij" and "B_ji <- B_ji U_ii^{-1}" for all panel
+// rows of level i: X <- X T^{-1} with X = P_i, T = Tu (blockIdx.y == 0) or
+// X = Qt_i, T = Tl (blockIdx.y == 1).  A workgroup holds RT = 32 (or 16)
+// panel rows; right-looking over 16-column chunks c: X_c <- X_c T_cc^{-1}
+// (inverted diagonal tile), then X_c' -= X_c T_cc' for the structurally
+// nonzero tiles c' > c.  Every product is a 16 x 16 x 16 FP64 MFMA block.
+// The rows live in LDS when RT x kp doubles fit, else in the panel itself.
+template <int RT, bool IN_LDS>
+__global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, const double *__restrict__ tri,
+                                                     const LevelDev *__restrict__ levels, int level,
+                                                     const int32_t *__restrict__ trow_ptr,
+                                                     const int32_t *__restrict__ trow_idx) {
+    extern __shared__ double xs_lds[];
+    const LevelDev L = levels[level];
+    const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
+    const int panel = blockIdx.y;
+    double *__restrict__ X = slab + (panel == 0 ? L.offP : L.offQ);
+    const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
+    const double *__restrict__ Tinv = tri + L.offT + 2 * (size_t)kp * kp + (size_t)panel * nt * 256;
+    const int32_t *__restrict__ tptr = trow_ptr + L.trow;
+    const int a0 = blockIdx.x * RT;
+    const int nrow = min(RT, m - a0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    constexpr int LD = RT + 1;
+    constexpr int NH = RT / 16;
+    // element (t, r) of the row block: column t of K space, row r
+    auto ld_x = [&](int t, int r) -> double {
+        if (IN_LDS) return xs_lds[t * LD + r];
+        return (r < nrow && t < kap) ? X[a0 + r + (size_t)t * m] : 0.0;
+    };
+    auto st_x = [&](int t, int r, double v) {
+        if (IN_LDS)
+            xs_lds[t * LD + r] = v;
+        else if (r < nrow && t < kap)
+            X[a0 + r + (size_t)t * m] = v;
+    };
+    if (IN_LDS) {
+        for (int e = tid; e < RT * kp; e += 256) {
+            const int t = e / RT, r = e - t * RT;
+            xs_lds[t * LD + r] = (r < nrow && t < kap) ? X[a0 + r + (size_t)t * m] : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int c = 0; c < nt; ++c) {
+        double4_t acc = {0, 0, 0, 0};
+        if (wave < NH) {
+            const int h = wave;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const double a = ld_x(16 * c + k, 16 * h + li);
+                const double bv = Tinv[(size_t)c * 256 + k * 16 + li];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (wave < NH) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) st_x(16 * c + li, 16 * wave + lk + 4 * r, acc[r]);
+        }
+        __syncthreads();
+        const int q0 = tptr[c], q1 = tptr[c + 1];
+        for (int q = wave; q < (q1 - q0) * NH; q += 4) {
+            const int cc = trow_idx[q0 + q / NH];
+            const int h = q % NH;
+            double4_t u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[r] = ld_x(16 * cc + li, 16 * h + lk + 4 * r);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const double a = -ld_x(16 * c + k, 16 * h + li);
+                const double bv = T[(size_t)(16 * c + k) * kp + 16 * cc + li];
+                u = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, u, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) st_x(16 * cc + li, 16 * h + lk + 4 * r, u[r]);
+        }
+        __syncthreads();
+    }
+    if (IN_LDS) {
+        for (int e = tid; e < RT * kap; e += 256) {
+            const int t = e / RT, r = e - t * RT;
+            if (r < nrow) X[a0 + r + (size_t)t * m] = xs_lds[t * LD + r];
+        }
+    }
+}
+
+hipError_t launch_panel_solve(const DevPlan &d, int level, int m, int kp, hipStream_t s) {
+    if (m <= 0 || kp <= 0) return hipSuccess;
+    const size_t lds32 = (size_t)33 * kp * sizeof(double), lds16 = (size_t)17 * kp * sizeof(double);
+    if (lds32 <= 150 * 1024) {
+        dim3 grid((unsigned)((m + 31) / 32), 2);
+        hipLaunchKernelGGL((k_panel_solve<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, level,
+                           d.trow_ptr, d.trow_idx);
+    } else if (lds16 <= 150 * 1024) {
+        dim3 grid((unsigned)((m + 15) / 16), 2);
+        hipLaunchKernelGGL((k_panel_solve<16, true>), grid, dim3(256), lds16, s, d.slab, d.tri, d.levels, level,
+                           d.trow_ptr, d.trow_idx);
+    } else {
+        dim3 grid((unsigned)((m + 15) / 16), 2);
+        hipLaunchKernelGGL((k_panel_solve<16, false>), grid, dim3(256), 0, s, d.slab, d.tri, d.levels, level,
+                           d.trow_ptr, d.trow_idx);
+    }
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------------- SSSSM
 // Alg. 1 "B_kj <- B_kj - B_ki B_ij" for every target (k, j) of level i: the
 // product P_i[a-segment] * Qt_i[b-segment]^T over the coupled index set,
@@ -528,6 +807,14 @@ hipError_t setup_kernel_attributes() {
     e = hipFuncSetAttribute((const void *)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_getrf_dense, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_panel_solve<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_panel_solve<16, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
     return e;
 }
 

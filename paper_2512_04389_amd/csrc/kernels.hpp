@@ -12,6 +12,9 @@ namespace slu {
 // Device view of the uploaded structure (all pointers inside the workspace).
 struct DevPlan {
     double *slab;
+    double *tri;                // compact coupled triangles (see LevelDev)
+    const int32_t *trow_ptr;
+    const int32_t *trow_idx;
     const LevelDev *levels;
     const int32_t *K_idx;
     const int32_t *R_idx;
@@ -42,6 +45,9 @@ hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s)
 hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
 hipError_t launch_getrf(const DevPlan &d, int level, int lds_bytes, hipStream_t s);
 hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hipStream_t s);
+hipError_t launch_getrf_dense(const DevPlan &d, int level, int b, hipStream_t s);
+hipError_t launch_tri_gather(const DevPlan &d, int level, int kp, hipStream_t s);
+hipError_t launch_panel_solve(const DevPlan &d, int level, int m, int kp, hipStream_t s);
 int trsm_rows_per_group(int kappa);
 hipError_t launch_ssssm(const DevPlan &d, int level, int64_t ntiles, hipStream_t s);
 

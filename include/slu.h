@@ -68,6 +68,11 @@ typedef struct slu_handle slu_handle;
 #define SLU_ORDER_GRID_ND 1       /* geometric nested dissection of a grid   */
 #define SLU_ORDER_USER 2          /* caller's permutation (new -> old)       */
 
+/* schedules of the level loop */
+#define SLU_SCHEDULE_WAVES 0      /* levels of equal height in the block
+                                     dependency tree run together           */
+#define SLU_SCHEDULE_LEVELS 1     /* strict level order of Algorithm 1       */
+
 /* blockings */
 #define SLU_BLOCK_IRREGULAR 0     /* Algorithm 3 on the sampled Algorithm 2 curve */
 #define SLU_BLOCK_REGULAR 1       /* fixed block size (Section 3.2)          */
@@ -85,6 +90,7 @@ typedef struct {
     int32_t ordering;             /* SLU_ORDER_*                             */
     int32_t grid_dims[3];         /* nx, ny, nz for SLU_ORDER_GRID_ND; grid
                                      point x + nx*(y + ny*z) is row/column i */
+    int32_t schedule;             /* SLU_SCHEDULE_WAVES | SLU_SCHEDULE_LEVELS */
     const int32_t *user_perm;     /* n entries for SLU_ORDER_USER; copied    */
 } slu_options;
 
@@ -108,7 +114,7 @@ typedef struct {
 } slu_info;
 
 /* Fill *opt with the defaults: irregular blocking, 1000 / 2 / 3 / 1,
- * natural ordering. */
+ * natural ordering, dependency-tree waves. */
 void slu_default_options(slu_options *opt);
 
 /* Analyze the pattern of A (host).  rowptr: int64[n+1]; colidx: int32[nnz],

@@ -37,7 +37,7 @@ class SparseLU:
 
     def __init__(self, n, rowptr, colidx, ordering="natural", grid_dims=None, perm=None,
                  blocking="irregular", block_size=0, sample_points=1000, step=2, max_num=3,
-                 advance=1):
+                 advance=1, schedule="waves"):
         self.n = int(n)
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self._colidx = np.ascontiguousarray(colidx, dtype=np.int32)
@@ -46,6 +46,7 @@ class SparseLU:
         opt.sample_points, opt.step, opt.max_num, opt.advance = sample_points, step, max_num, advance
         opt.blocking = {"irregular": SLU_BLOCK_IRREGULAR, "regular": SLU_BLOCK_REGULAR}[blocking]
         opt.regular_block = int(block_size)
+        opt.schedule = {"waves": _abi.SLU_SCHEDULE_WAVES, "levels": _abi.SLU_SCHEDULE_LEVELS}[schedule]
         self._perm_in = None
         if ordering == "natural":
             opt.ordering = SLU_ORDER_NATURAL

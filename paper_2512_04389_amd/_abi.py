@@ -31,6 +31,8 @@ SLU_ORDER_GRID_ND = 1
 SLU_ORDER_USER = 2
 SLU_BLOCK_IRREGULAR = 0
 SLU_BLOCK_REGULAR = 1
+SLU_SCHEDULE_WAVES = 0
+SLU_SCHEDULE_LEVELS = 1
 KERNELS = ("scatter", "getrf", "panel", "ssssm")
 
 EXPORTS = [
@@ -52,6 +54,7 @@ class slu_options(ctypes.Structure):
         ("regular_block", ctypes.c_int32),
         ("ordering", ctypes.c_int32),
         ("grid_dims", ctypes.c_int32 * 3),
+        ("schedule", ctypes.c_int32),
         ("user_perm", ctypes.c_void_p),
     ]
 

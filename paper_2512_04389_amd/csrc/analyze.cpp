@@ -207,6 +207,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
     if (opt.sample_points < 1 || opt.step < 1 || opt.max_num < 0 || opt.advance < 1)
         return SLU_ERR_ARG;
     if (opt.blocking != SLU_BLOCK_IRREGULAR && opt.blocking != SLU_BLOCK_REGULAR) return SLU_ERR_ARG;
+    if (opt.schedule != SLU_SCHEDULE_WAVES && opt.schedule != SLU_SCHEDULE_LEVELS) return SLU_ERR_ARG;
     if (opt.blocking == SLU_BLOCK_REGULAR && opt.regular_block < 1) return SLU_ERR_ARG;
 
     Analysis &an = *out;
@@ -364,33 +365,52 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             L.lds_getrf = (int32_t)((int64_t)b * b * 8);
             an.stored_flops += 2.0 / 3.0 * (double)b * b * b;
         } else {
-            int32_t w = 16;
-            while (w > 1 && ((int64_t)(w + b) * w + (int64_t)w * b) * 8 > kGetrfLdsBudget) w /= 2;
+            // widest chunk (16, 8, ...) whose panel and U part fit in LDS
+            std::vector<ChunkDev> best;
+            std::vector<int32_t> best_rows;
             int64_t maxl = 0;
-            std::vector<int32_t> rl;
-            for (int32_t c0 = 0; c0 < b; c0 += w) {
-                const int32_t ww = std::min(w, b - c0);
-                const int32_t c1 = c0 + ww;
-                const int32_t stamp = ++chunk_stamp;
-                rl.clear();
-                for (int32_t c = c0; c < c1; ++c) {
-                    const int64_t gc = r0 + c;
-                    for (int64_t q = an.s_colptr[gc] + 1; q < an.s_colptr[gc + 1]; ++q) {
-                        const int32_t r = an.s_rowidx[q];
-                        if (r >= r0 + b) break;
-                        if (r >= r0 + c1 && cmark[r] != stamp) {
-                            cmark[r] = stamp;
-                            rl.push_back(r - r0);
+            double sflops = 0.0;
+            for (int32_t w = 16; w >= 1; w /= 2) {
+                std::vector<ChunkDev> ch;
+                std::vector<int32_t> rows_all, rl;
+                int64_t ml = 0;
+                double fl = 0.0;
+                for (int32_t c0 = 0; c0 < b; c0 += w) {
+                    const int32_t ww = std::min(w, b - c0);
+                    const int32_t c1 = c0 + ww;
+                    const int32_t stamp = ++chunk_stamp;
+                    rl.clear();
+                    for (int32_t c = c0; c < c1; ++c) {
+                        const int64_t gc = r0 + c;
+                        for (int64_t q = an.s_colptr[gc] + 1; q < an.s_colptr[gc + 1]; ++q) {
+                            const int32_t r = an.s_rowidx[q];
+                            if (r >= r0 + b) break;
+                            if (r >= r0 + c1 && cmark[r] != stamp) {
+                                cmark[r] = stamp;
+                                rl.push_back(r - r0);
+                            }
                         }
                     }
+                    std::sort(rl.begin(), rl.end());
+                    ch.push_back(ChunkDev{c0, ww, (int32_t)rl.size(), 0, (int64_t)rows_all.size()});
+                    rows_all.insert(rows_all.end(), rl.begin(), rl.end());
+                    const int64_t nr = (int64_t)rl.size();
+                    ml = std::max<int64_t>(ml, ((int64_t)(ww + nr) * ww + (int64_t)(ww + 1) * nr) * 8 + 4 * nr);
+                    fl += 2.0 * (double)nr * nr * ww + (double)(ww + 2 * nr) * ww * ww;
                 }
-                std::sort(rl.begin(), rl.end());
-                an.chunks.push_back(ChunkDev{c0, ww, (int32_t)rl.size(), 0, (int64_t)an.chunk_rows.size()});
-                an.chunk_rows.insert(an.chunk_rows.end(), rl.begin(), rl.end());
-                const int64_t nr = (int64_t)rl.size();
-                maxl = std::max<int64_t>(maxl, ((int64_t)(ww + nr) * ww + (int64_t)ww * nr) * 8);
-                an.stored_flops += 2.0 * (double)nr * nr * ww + (double)(ww + nr) * ww * ww + (double)ww * ww * nr;
+                best.swap(ch);
+                best_rows.swap(rows_all);
+                maxl = ml;
+                sflops = fl;
+                if (ml <= kGetrfLdsBudget || w == 1) break;
             }
+            const int64_t base = (int64_t)an.chunk_rows.size();
+            for (ChunkDev &c : best) {
+                c.roff += base;
+                an.chunks.push_back(c);
+            }
+            an.chunk_rows.insert(an.chunk_rows.end(), best_rows.begin(), best_rows.end());
+            an.stored_flops += sflops;
             L.lds_getrf = (int32_t)maxl;
         }
         L.chunk_end = (int32_t)an.chunks.size();
@@ -499,6 +519,48 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
     }
     if ((int64_t)an.tasks.size() >= ((int64_t)1 << 31) || an.maps.size() >= ((size_t)1 << 40))
         return SLU_ERR_LIMIT;
+
+    // schedule: waves of levels with equal height in the dependency tree of
+    // the blocks.  Level i waits for every level j < i whose panels couple to
+    // block i (B_ij or B_ji nonempty, so SSSSM of j updates row / column i);
+    // height(i) = 1 + the largest height among those levels, so levels of one
+    // wave never update each other's rows or columns.
+    {
+        std::vector<int32_t> height(p, 0);
+        for (int64_t j = 0; j < p; ++j) {
+            const LevelDev &L = an.levels[j];
+            for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) {
+                const int32_t i = an.segs[sgi].blk;
+                height[i] = std::max(height[i], height[j] + 1);
+            }
+        }
+        int32_t H = 0;
+        for (int64_t i = 0; i < p; ++i) H = std::max(H, height[i] + 1);
+        std::vector<std::vector<int32_t>> byh;
+        if (opt.schedule == SLU_SCHEDULE_LEVELS) {
+            for (int64_t i = 0; i < p; ++i) byh.push_back({(int32_t)i});
+        } else {
+            byh.assign(H, {});
+            for (int64_t i = 0; i < p; ++i) byh[height[i]].push_back((int32_t)i);
+        }
+        for (const auto &lv : byh) {
+            if (lv.empty()) continue;
+            WaveInfo w{};
+            w.begin = (int32_t)an.wave_levels.size();
+            for (int32_t i : lv) {
+                const LevelDev &L = an.levels[i];
+                an.wave_levels.push_back(i);
+                const int32_t lds = L.b <= kLdsDenseMax ? (int32_t)((int64_t)L.b * (L.b | 1) * 8) : L.lds_getrf;
+                w.lds_getrf = std::max(w.lds_getrf, lds);
+                w.max_nt = std::max(w.max_nt, L.kp / 16);
+                w.max_kp = std::max(w.max_kp, L.kp);
+                w.max_m = std::max(w.max_m, L.m);
+                if (L.b <= kLdsDenseMax) w.any_dense = 1; else w.any_chunked = 1;
+            }
+            w.end = (int32_t)an.wave_levels.size();
+            an.waves.push_back(w);
+        }
+    }
 
     // slot of every entry of A in the slab
     an.slot.assign(an.nnz_a, -1);

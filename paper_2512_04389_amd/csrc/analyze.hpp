@@ -67,6 +67,18 @@ struct TileDev {
     int32_t tij;                // (ti << 16) | tj
 };
 
+// Levels that run together: equal height in the block dependency tree
+// (parent of block i = the first block below it coupled to it).  Launch
+// parameters are the maxima over the wave's levels.
+struct WaveInfo {
+    int32_t begin, end;         // range in wave_levels
+    int32_t lds_getrf;          // dynamic LDS bytes of the GETRF launch
+    int32_t max_nt;             // largest kp / 16
+    int32_t max_m;              // largest panel row count
+    int32_t max_kp;             // largest kp
+    int32_t any_dense, any_chunked;
+};
+
 struct Segment {
     int32_t blk, start, len;
 };
@@ -93,6 +105,8 @@ struct Analysis {
     std::vector<TaskDev> tasks;
     std::vector<int32_t> maps;
     std::vector<TileDev> tiles;
+    std::vector<WaveInfo> waves;
+    std::vector<int32_t> wave_levels;
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
     std::vector<int32_t> trow_idx;
     int64_t tri_doubles = 0;

@@ -17,7 +17,7 @@ struct slu_handle {
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
     size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_tasks, o_maps, o_tiles, o_slot, o_arow, o_acol,
-        o_atcol, o_atrow, o_atv, o_perm, o_info, o_scratch, o_norms;
+        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_norms;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
     std::vector<int64_t> at_vidx;
@@ -63,6 +63,7 @@ void plan_workspace(slu_handle *h) {
     h->o_atrow = take(h->at_rowidx.size() * 4);
     h->o_atv = take(h->at_vidx.size() * 8);
     h->o_perm = take(an.perm.size() * 4);
+    h->o_wlev = take(an.wave_levels.size() * 4);
     h->o_info = take(64);
     h->o_scratch = take((size_t)an.n * slu::kSolveCols * 8);
     h->o_norms = take(64 * 8);
@@ -203,6 +204,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_atrow, h->at_rowidx, s);
     if (e == hipSuccess) e = upload(base, h->o_atv, h->at_vidx, s);
     if (e == hipSuccess) e = upload(base, h->o_perm, an.perm, s);
+    if (e == hipSuccess) e = upload(base, h->o_wlev, an.wave_levels, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return SLU_ERR_HIP;
     slu::DevPlan &d = h->dev;
@@ -225,6 +227,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.at_rowidx = (const int32_t *)(base + h->o_atrow);
     d.at_vidx = (const int64_t *)(base + h->o_atv);
     d.perm = (const int32_t *)(base + h->o_perm);
+    d.wave_levels = (const int32_t *)(base + h->o_wlev);
     d.info = (unsigned long long *)(base + h->o_info);
     d.scratch = (double *)(base + h->o_scratch);
     d.norms = (unsigned long long *)(base + h->o_norms);
@@ -299,16 +302,19 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
     if (slu::launch_info_reset(d, s) != hipSuccess) return SLU_ERR_HIP;
     SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_zero(d.slab, an.slab_doubles, s));
     SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_scatter(d, values, s));
-    for (int64_t i = 0; i < an.p; ++i) {
-        const slu::LevelDev &L = an.levels[i];
-        if (L.b <= slu::kLdsDenseMax)
-            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_dense(d, (int)i, L.b, s));
-        else
-            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf(d, (int)i, L.lds_getrf, s));
-        if (L.kappa > 0) {
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather(d, (int)i, L.kp, s));
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve(d, (int)i, L.m, L.kp, s));
-            SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, (int)i, L.tile_end - L.tile_begin, s));
+    for (const slu::WaveInfo &w : an.waves) {
+        const int nlev = w.end - w.begin;
+        const int32_t *lv = d.wave_levels + w.begin;
+        SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
+        if (w.max_m > 0 && w.max_kp > 0) {
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, nlev, w.max_nt, s));
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
+        }
+        for (int q = w.begin; q < w.end; ++q) {
+            const int i = an.wave_levels[q];
+            const slu::LevelDev &L = an.levels[i];
+            if (L.kappa > 0)
+                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.tile_end - L.tile_begin, s));
         }
     }
 #undef SLU_TIMED

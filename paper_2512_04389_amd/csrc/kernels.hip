@@ -56,174 +56,166 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------- GETRF
-// Alg. 1 line "B_ii -> L_ii U_ii": no-pivot LU of the dense diagonal block,
-// one workgroup.  The block is processed in column chunks [c0, c0 + w):
-// the chunk's panel (its own rows plus the coupled rows R below it) is
-// factored in LDS, the chunk's U rows over R are forward-substituted, and the
-// trailing entries R x R are updated.  Entries outside the rows/columns R are
-// structurally untouched by the chunk.  Blocks of at most 128 rows are a
-// single chunk that lives entirely in LDS.
-__global__ __launch_bounds__(1024) void k_getrf(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                int level, const ChunkDev *__restrict__ chunks,
-                                                const int32_t *__restrict__ crows,
-                                                unsigned long long *__restrict__ info) {
-    extern __shared__ double lds[];
-    const LevelDev L = levels[level];
+// Alg. 1 line "B_ii -> L_ii U_ii" for diagonal blocks above 128 rows: no-pivot
+// LU of the dense diagonal block by one workgroup, right-looking over column
+// chunks [c0, c0 + w) (w <= 16).  Only the block rows R that S couples to a
+// chunk are touched by it:
+//   1. one wave factors the w x w diagonal of the chunk in registers;
+//   2. every thread takes one coupled row (L: x U_cc = a) or one coupled
+//      column (U: L_cc u = a) and solves it in registers;
+//   3. the four waves update the R x R trailing entries with FP64 MFMA.
+// Pivot divisions are FP64 divisions; a zero or non-finite pivot records its
+// permuted column in info[0].
+__device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict__ slab, const LevelDev &L, const ChunkDev *__restrict__ chunks,
+                              const int32_t *__restrict__ crows, double *lds,
+                              unsigned long long *__restrict__ info) {
     double *__restrict__ D = slab + L.offD;
     const int b = L.b;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     for (int ch = L.chunk_begin; ch < L.chunk_end; ++ch) {
         const ChunkDev C = chunks[ch];
         const int c0 = C.c0, w = C.w, nr = C.nr;
         const int32_t *__restrict__ R = crows + C.roff;
         const int T = w + nr;
-        double *Pn = lds;                      // Pn[j*T + t]: panel column j, panel row t
-        double *Ur = lds + (size_t)T * w;      // Ur[s*w + j]: U(c0 + j, R[s])
-        for (int e = tid; e < T * w; e += nt) {
-            const int j = e / T, t = e - j * T;
-            const int row = t < w ? c0 + t : R[t - w];
-            Pn[e] = D[row + (size_t)(c0 + j) * b];
-        }
-        __syncthreads();
-        for (int k = 0; k < w; ++k) {
-            const double piv = Pn[k * T + k];
-            if (tid == 0 && !(piv != 0.0 && isfinite(piv)))
-                atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
-            for (int t = k + 1 + tid; t < T; t += nt) Pn[k * T + t] = Pn[k * T + t] / piv;
-            __syncthreads();
-            const int rows = T - k - 1, cols = w - k - 1;
-            for (int e = tid; e < rows * cols; e += nt) {
-                const int jj = e / rows, tt = e - jj * rows;
-                const int j = k + 1 + jj, t = k + 1 + tt;
-                Pn[j * T + t] -= Pn[k * T + t] * Pn[j * T + k];
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < T * w; e += nt) {
-            const int j = e / T, t = e - j * T;
-            const int row = t < w ? c0 + t : R[t - w];
-            D[row + (size_t)(c0 + j) * b] = Pn[e];
-        }
-        if (nr > 0) {
-            for (int sI = tid; sI < nr; sI += nt) {
-                double u[16];
-                const size_t colo = (size_t)R[sI] * b;
+        const int wu = w + 1;
+        double *Pn = lds;                      // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
+        double *Uc = lds + (size_t)T * w;      // Uc[s*wu + j]: U(c0 + j, R[s])
+        int *Rs = (int *)(Uc + (size_t)nr * wu);   // the chunk's coupled rows
+        // one item per panel row (its w values) or per coupled column (its w
+        // values, contiguous in D): the loads of an item are issued together
+        for (int it = tid; it < T + nr; it += 256) {
+            double v[16];
+            if (it < T) {
+                const int row = it < w ? c0 + it : R[it - w];
+                if (it >= w) Rs[it - w] = row;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = j < w ? D[row + (size_t)(c0 + j) * b] : 0.0;
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
-                    if (j < w) u[j] = D[c0 + j + colo];
+                    if (j < w) Pn[j * T + it] = v[j];
+            } else {
+                const int sI = it - T;
+                const double *__restrict__ col = D + c0 + (size_t)R[sI] * b;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = j < w ? col[j] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) Uc[sI * wu + j] = v[j];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? Pn[j * T + lane] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < w) {
+                    // pivot row k (held by lane k): fetch all of it first so the
+                    // lane shuffles are issued back to back
+                    double u[16];
+#pragma unroll
+                    for (int j = k; j < 16; ++j) u[j] = __shfl(v[j], k, 64);
+                    const double piv = u[k];
+                    if (lane == 0 && !(piv != 0.0 && isfinite(piv)))
+                        atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
+                    if (lane > k) {
+                        const double l = v[k] / piv;
+                        v[k] = l;
+#pragma unroll
+                        for (int j = k + 1; j < 16; ++j) v[j] -= l * u[j];
+                    }
+                }
+            }
+            if (lane < w) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) {
+                        Pn[j * T + lane] = v[j];
+                        D[c0 + lane + (size_t)(c0 + j) * b] = v[j];
+                    }
+            }
+        }
+        __syncthreads();
+        for (int it = tid; it < 2 * nr; it += 256) {
+            double x[16];
+            if (it < nr) {
+                const int t = w + it;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) x[j] = j < w ? Pn[j * T + t] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j < w) {
+                        double v = x[j];
+#pragma unroll
+                        for (int jp = 0; jp < j; ++jp) v -= x[jp] * Pn[j * T + jp];
+                        x[j] = v / Pn[j * T + j];
+                    }
+                }
+                const size_t row = (size_t)Rs[it];
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) {
+                        Pn[j * T + t] = x[j];
+                        D[row + (size_t)(c0 + j) * b] = x[j];
+                    }
+            } else {
+                const int sI = it - nr;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) x[j] = j < w ? Uc[sI * wu + j] : 0.0;
 #pragma unroll
                 for (int j = 1; j < 16; ++j) {
                     if (j < w) {
-                        double v = u[j];
+                        double v = x[j];
 #pragma unroll
-                        for (int jp = 0; jp < j; ++jp) v -= Pn[jp * T + j] * u[jp];
-                        u[j] = v;
+                        for (int jp = 0; jp < j; ++jp) v -= Pn[jp * T + j] * x[jp];
+                        x[j] = v;
                     }
                 }
+                const size_t colo = (size_t)Rs[sI] * b;
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
                     if (j < w) {
-                        Ur[sI * w + j] = u[j];
-                        D[c0 + j + colo] = u[j];
+                        Uc[sI * wu + j] = x[j];
+                        D[c0 + j + colo] = x[j];
                     }
             }
-            __syncthreads();
-            for (int e = tid; e < nr * nr; e += nt) {
-                const int sI = e / nr, t = e - sI * nr;
-                double acc = 0.0;
-                for (int j = 0; j < w; ++j) acc += Pn[j * T + w + t] * Ur[sI * w + j];
-                D[R[t] + (size_t)R[sI] * b] -= acc;
-            }
         }
         __syncthreads();
-    }
-}
-
-hipError_t launch_getrf(const DevPlan &d, int level, int lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(k_getrf, dim3(1), dim3(1024), (size_t)lds_bytes, s, d.slab, d.levels, level, d.chunks,
-                       d.chunk_rows, d.info);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ GESSM / TSTRF
-// Alg. 1 "B_ij <- L_ii^{-1} B_ij" and "B_ji <- B_ji U_ii^{-1}" on the whole
-// U and L panels of level i.  On the coupled index set K_i both become a
-// right-side triangular solve X <- X T^{-1} of an m x kappa panel:
-//   L panel  (blockIdx.y == 0): X = P_i,  T = U_ii[K, K]          (pivot division)
-//   U panel  (blockIdx.y == 1): X = Qt_i, T = L_ii[K, K]^T        (unit diagonal)
-// One workgroup owns rt (16, 8, 4, 2 or 1) panel rows held in LDS, so that
-// kappa * rt doubles fit; the columns are processed in chunks of 16: a
-// product with the finished columns, then a 16-column triangular solve.
-__global__ __launch_bounds__(256) void k_trsm_panels(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                     int level, const int32_t *__restrict__ Kidx, int rt) {
-    extern __shared__ double xs[];  // xs[t*rt + r]
-    const LevelDev L = levels[level];
-    const int kap = L.kappa, m = L.m, b = L.b;
-    const bool lpanel = blockIdx.y == 0;
-    double *__restrict__ X = slab + (lpanel ? L.offP : L.offQ);
-    const double *__restrict__ D = slab + L.offD;
-    const int32_t *__restrict__ K = Kidx + L.Koff;
-    const int a0 = blockIdx.x * rt;
-    const int nrow = min(rt, m - a0);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < rt * kap; e += 256) {
-        const int t = e / rt, r = e - t * rt;
-        xs[e] = r < nrow ? X[a0 + r + (size_t)t * m] : 0.0;
-    }
-    __syncthreads();
-    const int r = tid % rt, jj = tid / rt;
-    for (int c0 = 0; c0 < kap; c0 += 16) {
-        const int cw = min(16, kap - c0);
-        if (jj < cw) {
-            const int col = c0 + jj;
-            const size_t Kc = (size_t)K[col];
-            double acc = 0.0;
-            if (lpanel) {
-                const double *__restrict__ Dc = D + Kc * b;     // U(K[t], K[col]) = D[K[t] + K[col]*b]
-                for (int t = 0; t < c0; ++t) acc += xs[t * rt + r] * Dc[K[t]];
-            } else {
-                const double *__restrict__ Dr = D + Kc;         // L(K[col], K[t]) = D[K[col] + K[t]*b]
-                for (int t = 0; t < c0; ++t) acc += xs[t * rt + r] * Dr[(size_t)K[t] * b];
+        const int ntl = (nr + 15) >> 4;
+        for (int q = wave; q < ntl * ntl; q += 4) {
+            const int ti = q / ntl, tj = q - ti * ntl;
+            const int sc = 16 * tj + li;
+            const bool vc = sc < nr;
+            const size_t colo = vc ? (size_t)Rs[sc] * b : 0;
+            double4_t acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ra = 16 * ti + lk + 4 * r;
+                acc[r] = (vc && ra < nr) ? D[Rs[ra] + colo] : 0.0;
             }
-            xs[col * rt + r] -= acc;
-        }
-        __syncthreads();
-        if (jj == 0) {
-            for (int j = 0; j < cw; ++j) {
-                const int col = c0 + j;
-                const size_t Kc = (size_t)K[col];
-                double v = xs[col * rt + r];
-                for (int jp = 0; jp < j; ++jp) {
-                    const size_t Kp = (size_t)K[c0 + jp];
-                    const double tv = lpanel ? D[Kp + Kc * b] : D[Kc + Kp * b];
-                    v -= xs[(c0 + jp) * rt + r] * tv;
+            const int ar = 16 * ti + li;
+            const bool va = ar < nr;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                if (4 * kk < w) {
+                    const double a = (k < w && va) ? -Pn[k * T + w + ar] : 0.0;
+                    const double bv = (k < w && vc) ? Uc[sc * wu + k] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
                 }
-                if (lpanel) v = v / D[Kc + Kc * b];
-                xs[col * rt + r] = v;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ra = 16 * ti + lk + 4 * r;
+                if (vc && ra < nr) D[Rs[ra] + colo] = acc[r];
             }
         }
         __syncthreads();
     }
-    for (int e = tid; e < rt * kap; e += 256) {
-        const int t = e / rt, rr = e - t * rt;
-        if (rr < nrow) X[a0 + rr + (size_t)t * m] = xs[e];
-    }
 }
 
-int trsm_rows_per_group(int kappa) {
-    int rt = 16;
-    while (rt > 1 && (int64_t)kappa * rt * 8 > 150 * 1024) rt /= 2;
-    return rt;
-}
-
-hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hipStream_t s) {
-    if (m <= 0 || kappa <= 0) return hipSuccess;
-    const int rt = trsm_rows_per_group(kappa);
-    dim3 grid((unsigned)((m + rt - 1) / rt), 2);
-    hipLaunchKernelGGL(k_trsm_panels, grid, dim3(256), (size_t)kappa * rt * sizeof(double), s, d.slab, d.levels,
-                       level, d.K_idx, rt);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------- dense GETRF (b <= 128)
 // Diagonal blocks of at most 128 rows: the whole block in LDS, blocked
@@ -231,17 +223,30 @@ hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hip
 // registers (each lane owns up to two rows; pivot row values are broadcast
 // with lane shuffles), all threads solve the panel's U rows, and the four
 // waves apply the trailing update as 16 x 16 FP64 MFMA tiles.
-__global__ __launch_bounds__(256) void k_getrf_dense(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                     int level, unsigned long long *__restrict__ info) {
-    extern __shared__ double ds[];
-    const LevelDev L = levels[level];
+__device__ void getrf_dense(double *__restrict__ slab, const LevelDev &L, double *ds,
+                            unsigned long long *__restrict__ info) {
     double *__restrict__ D = slab + L.offD;
     const int b = L.b;
     const int ldd = b | 1;                 // odd stride: conflict-free column-strided LDS access
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    for (int c = 0; c < b; ++c)
-        for (int r = tid; r < b; r += 256) ds[c * ldd + r] = D[r + (size_t)c * b];
+    const int bb = b * b;
+    for (int e0 = tid; e0 < bb; e0 += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u;
+            v[u] = e < bb ? D[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u;
+            if (e < bb) {
+                const int c = e / b;
+                ds[c * ldd + (e - c * b)] = v[u];
+            }
+        }
+    }
     __syncthreads();
     for (int c0 = 0; c0 < b; c0 += 16) {
         const int cw = min(16, b - c0);
@@ -257,17 +262,22 @@ __global__ __launch_bounds__(256) void k_getrf_dense(double *__restrict__ slab, 
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 if (k < cw) {
-                    const double piv = __shfl(v0[k], k, 64);
+                    // pivot row c0 + k (held by lane k): all shuffles issued first
+                    double u[16];
+#pragma unroll
+                    for (int j = k; j < 16; ++j) u[j] = __shfl(v0[j], k, 64);
+                    const double piv = u[k];
                     if (lane == 0 && !(piv != 0.0 && isfinite(piv)))
                         atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
-                    if (lane > k) v0[k] = v0[k] / piv;
-                    v1[k] = v1[k] / piv;
-                    const double l0 = v0[k], l1 = v1[k];
+                    const double l1 = v1[k] / piv;
+                    v1[k] = l1;
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) {
-                        const double u = __shfl(v0[j], k, 64);
-                        if (lane > k) v0[j] -= l0 * u;
-                        v1[j] -= l1 * u;
+                    for (int j = k + 1; j < 16; ++j) v1[j] -= l1 * u[j];
+                    if (lane > k) {
+                        const double l0 = v0[k] / piv;
+                        v0[k] = l0;
+#pragma unroll
+                        for (int j = k + 1; j < 16; ++j) v0[j] -= l0 * u[j];
                     }
                 }
             }
@@ -322,13 +332,30 @@ __global__ __launch_bounds__(256) void k_getrf_dense(double *__restrict__ slab, 
         }
         __syncthreads();
     }
-    for (int c = 0; c < b; ++c)
-        for (int r = tid; r < b; r += 256) D[r + (size_t)c * b] = ds[c * ldd + r];
+    for (int e = tid; e < bb; e += 256) {
+        const int c = e / b;
+        D[e] = ds[c * ldd + (e - c * b)];
+    }
 }
 
-hipError_t launch_getrf_dense(const DevPlan &d, int level, int b, hipStream_t s) {
-    const size_t lds = (size_t)b * (b | 1) * sizeof(double);
-    hipLaunchKernelGGL(k_getrf_dense, dim3(1), dim3(256), lds, s, d.slab, d.levels, level, d.info);
+// GETRF of every level of a wave: one workgroup per diagonal block, the
+// LDS-resident path for blocks up to 128 rows, the chunked path above.
+__global__ __launch_bounds__(256) void k_getrf_wave(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl,
+                                                    const ChunkDev *__restrict__ chunks,
+                                                    const int32_t *__restrict__ crows,
+                                                    unsigned long long *__restrict__ info) {
+    extern __shared__ double lds[];
+    const LevelDev L = levels[lvl[blockIdx.x]];
+    if (L.b <= 128)
+        getrf_dense(slab, L, lds, info);
+    else
+        getrf_chunked(slab, L, chunks, crows, lds, info);
+}
+
+hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_getrf_wave, dim3((unsigned)nlev), dim3(256), (size_t)lds_bytes, s, d.slab, d.levels, lvl,
+                       d.chunks, d.chunk_rows, d.info);
     return hipGetLastError();
 }
 
@@ -338,12 +365,14 @@ hipError_t launch_getrf_dense(const DevPlan &d, int level, int b, hipStream_t s)
 // from the factored diagonal block, then inverts the two diagonal tiles
 // (back substitution per column, FP64 divisions by the pivots).
 __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ slab, double *__restrict__ tri,
-                                                    const LevelDev *__restrict__ levels, int level,
+                                                    const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl,
                                                     const int32_t *__restrict__ Kidx) {
     __shared__ double du[16][17], dl[16][17];
-    const LevelDev L = levels[level];
+    const LevelDev L = levels[lvl[blockIdx.y]];
     const int kp = L.kp, kap = L.kappa, b = L.b, nt = kp >> 4;
     const int tr = blockIdx.x;
+    if (tr >= nt) return;
     const double *__restrict__ D = slab + L.offD;
     const int32_t *__restrict__ K = Kidx + L.Koff;
     double *__restrict__ Tu = tri + L.offT;
@@ -351,23 +380,36 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
     double *__restrict__ Iu = Tl + (size_t)kp * kp;
     double *__restrict__ Il = Iu + (size_t)nt * 256;
     const int width = kp - 16 * tr;
-    for (int e = threadIdx.x; e < 16 * width; e += 256) {
-        const int rr = e / width, cc = e - rr * width;
-        const int t1 = 16 * tr + rr, t2 = 16 * tr + cc;
-        double u, lt;
-        if (t1 < kap && t2 < kap) {
-            const size_t k1 = (size_t)K[t1], k2 = (size_t)K[t2];
-            u = t1 <= t2 ? D[k1 + k2 * b] : 0.0;
-            lt = t1 < t2 ? D[k2 + k1 * b] : (t1 == t2 ? 1.0 : 0.0);
-        } else {
-            u = t1 == t2 ? 1.0 : 0.0;
-            lt = u;
+    // thread (column cc, row rr): column index K[t2] from global once, then
+    // the 16 rows' values of U and L^T issued together
+    for (int cc = threadIdx.x; cc < width; cc += 256) {
+        const int t2 = 16 * tr + cc;
+        const bool c_in = t2 < kap;
+        const size_t k2 = c_in ? (size_t)K[t2] : 0;
+        double u[16], lt[16];
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int t1 = 16 * tr + rr;
+            const bool in = c_in && t1 < kap;
+            const size_t k1 = in ? (size_t)K[t1] : 0;
+            u[rr] = (in && t1 <= t2) ? D[k1 + k2 * b] : 0.0;
+            lt[rr] = (in && t1 < t2) ? D[k2 + k1 * b] : 0.0;
         }
-        Tu[(size_t)t1 * kp + t2] = u;
-        Tl[(size_t)t1 * kp + t2] = lt;
-        if (cc < 16) {
-            du[rr][cc] = u;
-            dl[rr][cc] = lt;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int t1 = 16 * tr + rr;
+            const bool in = c_in && t1 < kap;
+            double uu = u[rr], ll = lt[rr];
+            if (t1 == t2) {
+                ll = 1.0;
+                if (!in) uu = 1.0;
+            }
+            Tu[(size_t)t1 * kp + t2] = uu;
+            Tl[(size_t)t1 * kp + t2] = ll;
+            if (cc < 16) {
+                du[rr][cc] = uu;
+                dl[rr][cc] = ll;
+            }
         }
     }
     __syncthreads();
@@ -388,10 +430,10 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
     }
 }
 
-hipError_t launch_tri_gather(const DevPlan &d, int level, int kp, hipStream_t s) {
-    if (kp <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)(kp / 16)), dim3(256), 0, s, d.slab, d.tri, d.levels, level,
-                       d.K_idx);
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s) {
+    if (max_nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)max_nt, (unsigned)nlev), dim3(256), 0, s, d.slab, d.tri,
+                       d.levels, lvl, d.K_idx);
     return hipGetLastError();
 }
 
@@ -405,12 +447,14 @@ hipError_t launch_tri_gather(const DevPlan &d, int level, int kp, hipStream_t s)
 // The rows live in LDS when RT x kp doubles fit, else in the panel itself.
 template <int RT, bool IN_LDS>
 __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, const double *__restrict__ tri,
-                                                     const LevelDev *__restrict__ levels, int level,
+                                                     const LevelDev *__restrict__ levels,
+                                                     const int32_t *__restrict__ lvl,
                                                      const int32_t *__restrict__ trow_ptr,
                                                      const int32_t *__restrict__ trow_idx) {
     extern __shared__ double xs_lds[];
-    const LevelDev L = levels[level];
+    const LevelDev L = levels[lvl[blockIdx.z]];
     const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
+    if (kp == 0 || (int)blockIdx.x * RT >= m) return;
     const int panel = blockIdx.y;
     double *__restrict__ X = slab + (panel == 0 ? L.offP : L.offQ);
     const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
@@ -434,9 +478,20 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
             X[a0 + r + (size_t)t * m] = v;
     };
     if (IN_LDS) {
-        for (int e = tid; e < RT * kp; e += 256) {
-            const int t = e / RT, r = e - t * RT;
-            xs_lds[t * LD + r] = (r < nrow && t < kap) ? X[a0 + r + (size_t)t * m] : 0.0;
+        // column t of the row block is RT contiguous doubles of X
+        for (int t0 = tid / RT; t0 < kp; t0 += 8 * (256 / RT)) {
+            const int r = tid % RT;
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u * (256 / RT);
+                v[u] = (r < nrow && t < kap) ? X[a0 + r + (size_t)t * m] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u * (256 / RT);
+                if (t < kp) xs_lds[t * LD + r] = v[u];
+            }
         }
         __syncthreads();
     }
@@ -485,20 +540,21 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
     }
 }
 
-hipError_t launch_panel_solve(const DevPlan &d, int level, int m, int kp, hipStream_t s) {
-    if (m <= 0 || kp <= 0) return hipSuccess;
-    const size_t lds32 = (size_t)33 * kp * sizeof(double), lds16 = (size_t)17 * kp * sizeof(double);
+hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
+                                   hipStream_t s) {
+    if (max_m <= 0 || max_kp <= 0) return hipSuccess;
+    const size_t lds32 = (size_t)33 * max_kp * sizeof(double), lds16 = (size_t)17 * max_kp * sizeof(double);
     if (lds32 <= 150 * 1024) {
-        dim3 grid((unsigned)((m + 31) / 32), 2);
-        hipLaunchKernelGGL((k_panel_solve<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, level,
+        dim3 grid((unsigned)((max_m + 31) / 32), 2, (unsigned)nlev);
+        hipLaunchKernelGGL((k_panel_solve<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, lvl,
                            d.trow_ptr, d.trow_idx);
     } else if (lds16 <= 150 * 1024) {
-        dim3 grid((unsigned)((m + 15) / 16), 2);
-        hipLaunchKernelGGL((k_panel_solve<16, true>), grid, dim3(256), lds16, s, d.slab, d.tri, d.levels, level,
+        dim3 grid((unsigned)((max_m + 15) / 16), 2, (unsigned)nlev);
+        hipLaunchKernelGGL((k_panel_solve<16, true>), grid, dim3(256), lds16, s, d.slab, d.tri, d.levels, lvl,
                            d.trow_ptr, d.trow_idx);
     } else {
-        dim3 grid((unsigned)((m + 15) / 16), 2);
-        hipLaunchKernelGGL((k_panel_solve<16, false>), grid, dim3(256), 0, s, d.slab, d.tri, d.levels, level,
+        dim3 grid((unsigned)((max_m + 15) / 16), 2, (unsigned)nlev);
+        hipLaunchKernelGGL((k_panel_solve<16, false>), grid, dim3(256), 0, s, d.slab, d.tri, d.levels, lvl,
                            d.trow_ptr, d.trow_idx);
     }
     return hipGetLastError();
@@ -536,18 +592,40 @@ __global__ __launch_bounds__(64) void k_ssssm(double *__restrict__ slab, const L
     const double *__restrict__ qb0 = Q + T.b0 + bc0;
     const double *__restrict__ qb1 = Q + T.b0 + bc1;
     double4_t c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-    for (int k0 = 0; k0 < kap; k0 += 4) {
-        const int k = k0 + lk;
-        const bool vk = k < kap;
-        const size_t ko = (size_t)k * m;
-        const double a0 = (va0 && vk) ? pa0[ko] : 0.0;
-        const double a1 = (va1 && vk) ? pa1[ko] : 0.0;
-        const double b0 = (vb0 && vk) ? qb0[ko] : 0.0;
-        const double b1 = (vb1 && vk) ? qb1[ko] : 0.0;
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+    // operands of 4 k-steps (16 inner indices) are loaded together, one
+    // group ahead of the MFMAs that consume them
+    constexpr int G = 4;
+    double a0[G], a1[G], b0[G], b1[G];
+    auto load_group = [&](int kg) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = kg + 4 * g + lk;
+            const bool vk = k < kap;
+            const size_t ko = (size_t)k * m;
+            a0[g] = (va0 && vk) ? pa0[ko] : 0.0;
+            a1[g] = (va1 && vk) ? pa1[ko] : 0.0;
+            b0[g] = (vb0 && vk) ? qb0[ko] : 0.0;
+            b1[g] = (vb1 && vk) ? qb1[ko] : 0.0;
+        }
+    };
+    load_group(0);
+    for (int kg = 0; kg < kap; kg += 4 * G) {
+        double ca0[G], ca1[G], cb0[G], cb1[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ca0[g] = a0[g];
+            ca1[g] = a1[g];
+            cb0[g] = b0[g];
+            cb1[g] = b1[g];
+        }
+        if (kg + 4 * G < kap) load_group(kg + 4 * G);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[g], cb0[g], c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[g], cb1[g], c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[g], cb0[g], c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[g], cb1[g], c11, 0, 0, 0);
+        }
     }
     const int32_t *__restrict__ rmap = maps + T.rmap;
     const int32_t *__restrict__ cmap = maps + T.cmap;
@@ -800,15 +878,11 @@ hipError_t launch_residual_norms(const DevPlan &d, const double *values, const d
 
 hipError_t setup_kernel_attributes() {
     hipError_t e;
-    e = hipFuncSetAttribute((const void *)k_getrf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_trsm_panels, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_getrf_dense, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    e = hipFuncSetAttribute((const void *)k_getrf_wave, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_panel_solve<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);

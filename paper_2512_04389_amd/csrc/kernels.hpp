@@ -30,6 +30,7 @@ struct DevPlan {
     const int32_t *at_rowidx;   // CSC of A: row of every entry
     const int64_t *at_vidx;     // CSC of A: index of the entry in CSR order
     const int32_t *perm;
+    const int32_t *wave_levels; // levels of every wave, consecutive
     unsigned long long *info;   // [0] smallest failed pivot column (or ~0)
     double *scratch;            // n * kSolveCols doubles
     unsigned long long *norms;  // 4 * kSolveCols (non-negative doubles as bits)
@@ -43,12 +44,10 @@ hipError_t setup_kernel_attributes();
 hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);
 hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
-hipError_t launch_getrf(const DevPlan &d, int level, int lds_bytes, hipStream_t s);
-hipError_t launch_trsm_panels(const DevPlan &d, int level, int m, int kappa, hipStream_t s);
-hipError_t launch_getrf_dense(const DevPlan &d, int level, int b, hipStream_t s);
-hipError_t launch_tri_gather(const DevPlan &d, int level, int kp, hipStream_t s);
-hipError_t launch_panel_solve(const DevPlan &d, int level, int m, int kp, hipStream_t s);
-int trsm_rows_per_group(int kappa);
+hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s);
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s);
+hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
+                                   hipStream_t s);
 hipError_t launch_ssssm(const DevPlan &d, int level, int64_t ntiles, hipStream_t s);
 
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).

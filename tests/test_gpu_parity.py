@@ -51,6 +51,14 @@ def test_convection_diffusion_16():
     run_case("convdiff-16", n, rp, ci, v, nrhs=17, ordering="grid_nd", grid_dims=(16, 16, 16))
 
 
+def test_strict_level_schedule():
+    n, rp, ci, v = synth.convection_diffusion_3d(14)
+    run_case("convdiff-14-levels", n, rp, ci, v, ordering="grid_nd", grid_dims=(14, 14, 14),
+             schedule="levels")
+    run_case("convdiff-14-regular-300-levels", n, rp, ci, v, ordering="grid_nd", grid_dims=(14, 14, 14),
+             blocking="regular", block_size=300, schedule="levels")
+
+
 @pytest.mark.parametrize("b", [37, 200, 700])
 def test_regular_blocking_chunked_getrf(b):
     # b > 128 exercises the chunked GETRF path; 37 leaves a ragged last block

@@ -368,12 +368,12 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             // widest chunk (16, 8, ...) whose panel and U part fit in LDS
             std::vector<ChunkDev> best;
             std::vector<int32_t> best_rows;
-            int64_t maxl = 0;
+            int64_t maxl = 0, best_mnr = 0;
             double sflops = 0.0;
             for (int32_t w = 16; w >= 1; w /= 2) {
                 std::vector<ChunkDev> ch;
                 std::vector<int32_t> rows_all, rl;
-                int64_t ml = 0;
+                int64_t ml = 0, mnr = 0;
                 double fl = 0.0;
                 for (int32_t c0 = 0; c0 < b; c0 += w) {
                     const int32_t ww = std::min(w, b - c0);
@@ -395,12 +395,16 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                     ch.push_back(ChunkDev{c0, ww, (int32_t)rl.size(), 0, (int64_t)rows_all.size()});
                     rows_all.insert(rows_all.end(), rl.begin(), rl.end());
                     const int64_t nr = (int64_t)rl.size();
-                    ml = std::max<int64_t>(ml, ((int64_t)(ww + nr) * ww + (int64_t)(ww + 1) * nr) * 8 + 4 * nr);
+                    ml = std::max<int64_t>(ml, ((int64_t)(ww + nr) * ww + (int64_t)(ww + 1) * nr) * 8);
+                    mnr = std::max<int64_t>(mnr, nr);
                     fl += 2.0 * (double)nr * nr * ww + (double)(ww + 2 * nr) * ww * ww;
                 }
                 best.swap(ch);
                 best_rows.swap(rows_all);
+                // two coupled-row buffers (ints) precede the chunk's panel
+                ml += ((2 * mnr + 1) / 2) * 8 + 2 * 16 * 17 * 8;   // + the two 16 x 16 inverses
                 maxl = ml;
+                best_mnr = mnr;
                 sflops = fl;
                 if (ml <= kGetrfLdsBudget || w == 1) break;
             }
@@ -412,6 +416,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             an.chunk_rows.insert(an.chunk_rows.end(), best_rows.begin(), best_rows.end());
             an.stored_flops += sflops;
             L.lds_getrf = (int32_t)maxl;
+            L.pad = (int32_t)best_mnr;
         }
         L.chunk_end = (int32_t)an.chunks.size();
     }
@@ -455,7 +460,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         an.tri_doubles = toff;
     }
 
-    // SSSSM tasks, maps and tiles
+    // SSSSM tasks and maps
     for (int64_t i = 0; i < p; ++i) {
         LevelDev &L = an.levels[i];
         L.task_begin = (int64_t)an.tasks.size();

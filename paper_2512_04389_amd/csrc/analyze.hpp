@@ -41,7 +41,7 @@ struct LevelDev {
     int32_t lds_getrf;          // dynamic LDS bytes for GETRF
     int32_t kp;                 // kappa rounded up to a multiple of 16
     int32_t trow;               // offset into trow_ptr
-    int32_t pad;
+    int32_t pad;                // chunked GETRF: largest coupled-row count of a chunk
 };
 
 // One column chunk of the right-looking GETRF of D_i: local columns
@@ -61,12 +61,6 @@ struct TaskDev {
     int32_t a0, alen, b0, blen;
 };
 
-// Output tile of the SSSSM GEMM of a level.
-struct TileDev {
-    int32_t task;
-    int32_t tij;                // (ti << 16) | tj
-};
-
 // Levels that run together: equal height in the block dependency tree
 // (parent of block i = the first block below it coupled to it).  Launch
 // parameters are the maxima over the wave's levels.
@@ -77,6 +71,12 @@ struct WaveInfo {
     int32_t max_m;              // largest panel row count
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
+};
+
+// Output tile (32 x 32) of one SSSSM task.
+struct TileDev {
+    int32_t task;
+    int32_t tij;                // (ti << 16) | tj
 };
 
 struct Segment {

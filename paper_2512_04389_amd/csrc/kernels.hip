@@ -16,6 +16,97 @@ namespace slu {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// Value of a lane's double in every lane (the lane index must be the same in
+// all lanes of the wave): two v_readlane into scalar registers.
+__device__ __forceinline__ double bcast_lane(double v, int k) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, k);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1 / x in FP64: hardware estimate refined by two Newton steps (relative
+// error within a few ulps; used where a pivot's reciprocal scales a column).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// In-place no-pivot LU of the w x w (w <= 16) leading block of the LDS array
+// A (element (i, j) at A[j * lda + i]) by wave 0: lane i holds row i, the
+// pivot row is broadcast with readlane.  Records a zero / non-finite pivot.
+__device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, int col0,
+                                           unsigned long long *__restrict__ info) {
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? A[j * lda + lane] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < w) {
+            double u[16];
+#pragma unroll
+            for (int j = k; j < 16; ++j) u[j] = bcast_lane(v[j], k);
+            const double piv = u[k];
+            if (lane == 0 && !(piv != 0.0 && isfinite(piv))) atomicMin(info, (unsigned long long)(col0 + k));
+            const double rp = recip(piv);
+            if (lane > k) {
+                const double l = v[k] * rp;
+                v[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < 16; ++j) v[j] -= l * u[j];
+            }
+        }
+    }
+    if (lane < w) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < w) A[j * lda + lane] = v[j];
+    }
+}
+
+// Inverses of the factors of a w x w LU held in LDS (as left by lu16_wave0),
+// by wave 0: lane j < 16 forms column j of U^{-1}, lane 16 + j column j of
+// L^{-1} (unit lower).  Ui / Li are 16 x 16 with row stride 17, element
+// (r, c) at [r * 17 + c]; rows / columns beyond w are the identity.
+__device__ __forceinline__ void tri_inverses16_wave0(const double *A, int lda, int w, int lane, double *Ui,
+                                                     double *Li) {
+    if (lane >= 32) return;
+    const int j = lane & 15;
+    double x[16];
+    if (lane < 16) {
+        double rd[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rd[i] = i < w ? recip(A[i * lda + i]) : 1.0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            double sacc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 15; t > i; --t) {
+                const double uit = (i < w && t < w) ? A[t * lda + i] : 0.0;
+                sacc -= uit * x[t];
+            }
+            x[i] = (i <= j) ? sacc * rd[i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Ui[i * 17 + j] = x[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            double sacc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 0; t < i; ++t) {
+                const double lit = (i < w && t < w) ? A[t * lda + i] : 0.0;
+                sacc -= lit * x[t];
+            }
+            x[i] = (i >= j) ? sacc : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Li[i * 17 + j] = x[i];
+    }
+}
+
 // ------------------------------------------------------------------ helpers
 __global__ void k_zero(double *__restrict__ p, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -60,35 +151,47 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 // LU of the dense diagonal block by one workgroup, right-looking over column
 // chunks [c0, c0 + w) (w <= 16).  Only the block rows R that S couples to a
 // chunk are touched by it:
-//   1. one wave factors the w x w diagonal of the chunk in registers;
-//   2. every thread takes one coupled row (L: x U_cc = a) or one coupled
-//      column (U: L_cc u = a) and solves it in registers;
+//   1. wave 0 factors the w x w diagonal of the chunk in registers and forms
+//      the inverses of its two triangles;
+//   2. the coupled rows (L = A U_cc^{-1}) and coupled columns
+//      (U = L_cc^{-1} A) are 16 x 16 x 16 FP64 MFMA products;
 //   3. the four waves update the R x R trailing entries with FP64 MFMA.
 // Pivot divisions are FP64 divisions; a zero or non-finite pivot records its
 // permuted column in info[0].
-__device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict__ slab, const LevelDev &L, const ChunkDev *__restrict__ chunks,
-                              const int32_t *__restrict__ crows, double *lds,
-                              unsigned long long *__restrict__ info) {
+__device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict__ slab, const LevelDev &L,
+                                                              const ChunkDev *__restrict__ chunks,
+                                                              const int32_t *__restrict__ crows, double *lds,
+                                                              unsigned long long *__restrict__ info) {
     double *__restrict__ D = slab + L.offD;
     const int b = L.b;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
+    const int maxnr = L.pad;                    // largest coupled-row count of a chunk
+    int *Rbuf0 = (int *)lds;                    // coupled rows of the current / next chunk
+    int *Rbuf1 = Rbuf0 + maxnr;
+    double *Ui = lds + ((2 * maxnr + 1) >> 1);  // 16 x 17 inverse of U_cc
+    double *Li = Ui + 16 * 17;                  // 16 x 17 inverse of L_cc
+    double *work = Li + 16 * 17;
+    {
+        const ChunkDev C = chunks[L.chunk_begin];
+        for (int q = tid; q < C.nr; q += 256) Rbuf0[q] = crows[C.roff + q];
+    }
+    __syncthreads();
     for (int ch = L.chunk_begin; ch < L.chunk_end; ++ch) {
         const ChunkDev C = chunks[ch];
         const int c0 = C.c0, w = C.w, nr = C.nr;
-        const int32_t *__restrict__ R = crows + C.roff;
+        const int *Rs = ((ch - L.chunk_begin) & 1) ? Rbuf1 : Rbuf0;
+        int *Rn = ((ch - L.chunk_begin) & 1) ? Rbuf0 : Rbuf1;
         const int T = w + nr;
         const int wu = w + 1;
-        double *Pn = lds;                      // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
-        double *Uc = lds + (size_t)T * w;      // Uc[s*wu + j]: U(c0 + j, R[s])
-        int *Rs = (int *)(Uc + (size_t)nr * wu);   // the chunk's coupled rows
+        double *Pn = work;                     // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
+        double *Uc = work + (size_t)T * w;     // Uc[s*wu + j]: U(c0 + j, Rs[s])
         // one item per panel row (its w values) or per coupled column (its w
         // values, contiguous in D): the loads of an item are issued together
         for (int it = tid; it < T + nr; it += 256) {
             double v[16];
             if (it < T) {
-                const int row = it < w ? c0 + it : R[it - w];
-                if (it >= w) Rs[it - w] = row;
+                const int row = it < w ? c0 + it : Rs[it - w];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) v[j] = j < w ? D[row + (size_t)(c0 + j) * b] : 0.0;
 #pragma unroll
@@ -96,7 +199,7 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
                     if (j < w) Pn[j * T + it] = v[j];
             } else {
                 const int sI = it - T;
-                const double *__restrict__ col = D + c0 + (size_t)R[sI] * b;
+                const double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
 #pragma unroll
                 for (int j = 0; j < 16; ++j) v[j] = j < w ? col[j] : 0.0;
 #pragma unroll
@@ -106,116 +209,124 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
         }
         __syncthreads();
         if (wave == 0) {
-            double v[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? Pn[j * T + lane] : 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k < w) {
-                    // pivot row k (held by lane k): fetch all of it first so the
-                    // lane shuffles are issued back to back
-                    double u[16];
-#pragma unroll
-                    for (int j = k; j < 16; ++j) u[j] = __shfl(v[j], k, 64);
-                    const double piv = u[k];
-                    if (lane == 0 && !(piv != 0.0 && isfinite(piv)))
-                        atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
-                    if (lane > k) {
-                        const double l = v[k] / piv;
-                        v[k] = l;
-#pragma unroll
-                        for (int j = k + 1; j < 16; ++j) v[j] -= l * u[j];
-                    }
-                }
-            }
+            lu16_wave0(Pn, T, w, lane, L.r0 + c0, info);
+        } else if (ch + 1 < L.chunk_end) {
+            // the other waves fetch the next chunk's coupled rows meanwhile
+            const ChunkDev Cn = chunks[ch + 1];
+            for (int q = tid - 64; q < Cn.nr; q += 192) Rn[q] = crows[Cn.roff + q];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            tri_inverses16_wave0(Pn, T, w, lane, Ui, Li);
             if (lane < w) {
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
-                    if (j < w) {
-                        Pn[j * T + lane] = v[j];
-                        D[c0 + lane + (size_t)(c0 + j) * b] = v[j];
-                    }
+                    if (j < w) D[c0 + lane + (size_t)(c0 + j) * b] = Pn[j * T + lane];
             }
         }
         __syncthreads();
-        for (int it = tid; it < 2 * nr; it += 256) {
-            double x[16];
-            if (it < nr) {
-                const int t = w + it;
+        // coupled rows and columns: 16 x 16 output tiles, four waves
+        const int nrt = (nr + 15) >> 4;
+        for (int q = wave; q < 2 * nrt; q += 4) {
+            double4_t acc = {0, 0, 0, 0};
+            if (q < nrt) {
+                // L rows, transposed: X^T = U^{-T} A_rows^T, output element
+                // (chunk column lk + 4r, coupled row 16q + li)
+                const int ar = 16 * q + li;
 #pragma unroll
-                for (int j = 0; j < 16; ++j) x[j] = j < w ? Pn[j * T + t] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    if (j < w) {
-                        double v = x[j];
-#pragma unroll
-                        for (int jp = 0; jp < j; ++jp) v -= x[jp] * Pn[j * T + jp];
-                        x[j] = v / Pn[j * T + j];
-                    }
-                }
-                const size_t row = (size_t)Rs[it];
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < w) {
-                        Pn[j * T + t] = x[j];
-                        D[row + (size_t)(c0 + j) * b] = x[j];
-                    }
-            } else {
-                const int sI = it - nr;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) x[j] = j < w ? Uc[sI * wu + j] : 0.0;
-#pragma unroll
-                for (int j = 1; j < 16; ++j) {
-                    if (j < w) {
-                        double v = x[j];
-#pragma unroll
-                        for (int jp = 0; jp < j; ++jp) v -= Pn[jp * T + j] * x[jp];
-                        x[j] = v;
-                    }
-                }
-                const size_t colo = (size_t)Rs[sI] * b;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < w) {
-                        Uc[sI * wu + j] = x[j];
-                        D[c0 + j + colo] = x[j];
-                    }
-            }
-        }
-        __syncthreads();
-        const int ntl = (nr + 15) >> 4;
-        for (int q = wave; q < ntl * ntl; q += 4) {
-            const int ti = q / ntl, tj = q - ti * ntl;
-            const int sc = 16 * tj + li;
-            const bool vc = sc < nr;
-            const size_t colo = vc ? (size_t)Rs[sc] * b : 0;
-            double4_t acc;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ra = 16 * ti + lk + 4 * r;
-                acc[r] = (vc && ra < nr) ? D[Rs[ra] + colo] : 0.0;
-            }
-            const int ar = 16 * ti + li;
-            const bool va = ar < nr;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * kk + lk;
-                if (4 * kk < w) {
-                    const double a = (k < w && va) ? -Pn[k * T + w + ar] : 0.0;
-                    const double bv = (k < w && vc) ? Uc[sc * wu + k] : 0.0;
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    const double a = Ui[k * 17 + li];                       // (U^{-T})[li][k]
+                    const double bv = (k < w && ar < nr) ? Pn[k * T + w + ar] : 0.0;
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
                 }
+                if (ar < nr) {
+                    const size_t row = (size_t)Rs[ar];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = lk + 4 * r;
+                        if (j < w) {
+                            Pn[j * T + w + ar] = acc[r];
+                            D[row + (size_t)(c0 + j) * b] = acc[r];
+                        }
+                    }
+                }
+            } else {
+                // U columns, transposed: Y^T = A_cols^T L^{-T}, output element
+                // (coupled column 16q' + lk + 4r, chunk row li)
+                const int qq = q - nrt;
+                const int sc = 16 * qq + li;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    const double a = (k < w && sc < nr) ? Uc[sc * wu + k] : 0.0;   // (A_cols^T)[li][k]
+                    const double bv = Li[li * 17 + k];                                // (L^{-T})[k][li]
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int s2 = 16 * qq + lk + 4 * r;
+                    if (s2 < nr && li < w) {
+                        Uc[s2 * wu + li] = acc[r];
+                        D[c0 + li + (size_t)Rs[s2] * b] = acc[r];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // trailing update of the coupled rows x coupled columns: each wave
+        // loads all entries of up to eight of its 16 x 16 tiles, then applies
+        // the rank-w product on MFMA and stores them back
+        const int ntl = nrt;
+        const int ntiles = ntl * ntl;
+        for (int q0 = wave; q0 < ntiles; q0 += 32) {
+            double4_t acc[8];
+            bool vc[8];
+            // transposed tiles: output element (coupled column 16tj + lk + 4r,
+            // coupled row 16ti + li), so the 16 lanes of a group read and
+            // write consecutive rows of one column of D
+            size_t rowo[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 4 * u;
+                const int ti = q / ntl, tj = q - ti * ntl;
+                const int ra = 16 * ti + li;
+                vc[u] = q < ntiles && ra < nr;
+                rowo[u] = vc[u] ? (size_t)Rs[ra] : 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int sc = 16 * tj + lk + 4 * r;
+                    acc[u][r] = (vc[u] && sc < nr) ? D[rowo[u] + (size_t)Rs[sc] * b] : 0.0;
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ra = 16 * ti + lk + 4 * r;
-                if (vc && ra < nr) D[Rs[ra] + colo] = acc[r];
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 4 * u;
+                if (q < ntiles) {
+                    const int ti = q / ntl, tj = q - ti * ntl;
+                    const int sc = 16 * tj + li;
+                    const int ar = 16 * ti + li;
+                    const bool va = ar < nr, vcc = sc < nr;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 4 * kk + lk;
+                        if (4 * kk < w) {
+                            const double a = (k < w && vcc) ? -Uc[sc * wu + k] : 0.0;   // (U^T)[sc][k]
+                            const double bv = (k < w && va) ? Pn[k * T + w + ar] : 0.0;  // (L^T)[k][ar]
+                            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int sc2 = 16 * tj + lk + 4 * r;
+                        if (vc[u] && sc2 < nr) D[rowo[u] + (size_t)Rs[sc2] * b] = acc[u][r];
+                    }
+                }
             }
         }
         __syncthreads();
     }
 }
-
 
 // ------------------------------------------------- dense GETRF (b <= 128)
 // Diagonal blocks of at most 128 rows: the whole block in LDS, blocked

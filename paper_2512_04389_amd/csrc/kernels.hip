@@ -66,47 +66,46 @@ __device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, 
     }
 }
 
-// Inverses of the factors of a w x w LU held in LDS (as left by lu16_wave0),
-// by wave 0: lane j < 16 forms column j of U^{-1}, lane 16 + j column j of
-// L^{-1} (unit lower).  Ui / Li are 16 x 16 with row stride 17, element
-// (r, c) at [r * 17 + c]; rows / columns beyond w are the identity.
-__device__ __forceinline__ void tri_inverses16_wave0(const double *A, int lda, int w, int lane, double *Ui,
-                                                     double *Li) {
-    if (lane >= 32) return;
-    const int j = lane & 15;
+// Inverses of the factors of a w x w LU held in LDS (as left by lu16_wave0).
+// Lane j < 16 of the calling wave forms column j of U^{-1} (upper == true)
+// or of L^{-1} (unit lower); the two are meant to run in different waves.
+// Ui / Li are 16 x 16 with row stride 17, element (r, c) at [r * 17 + c];
+// rows / columns beyond w are the identity.  Each triangle row is read from
+// LDS as one batch before its products.
+__device__ __forceinline__ void tri_inverse16(const double *A, int lda, int w, int lane, bool upper,
+                                              double *Out) {
+    if (lane >= 16) return;
+    const int j = lane;
     double x[16];
-    if (lane < 16) {
+    if (upper) {
         double rd[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) rd[i] = i < w ? recip(A[i * lda + i]) : 1.0;
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
+            double row[16];
+#pragma unroll
+            for (int t = i + 1; t < 16; ++t) row[t] = (i < w && t < w) ? A[t * lda + i] : 0.0;
             double sacc = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-            for (int t = 15; t > i; --t) {
-                const double uit = (i < w && t < w) ? A[t * lda + i] : 0.0;
-                sacc -= uit * x[t];
-            }
+            for (int t = 15; t > i; --t) sacc -= row[t] * x[t];
             x[i] = (i <= j) ? sacc * rd[i] : 0.0;
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) Ui[i * 17 + j] = x[i];
     } else {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
+            double row[16];
+#pragma unroll
+            for (int t = 0; t < i; ++t) row[t] = (i < w && t < w) ? A[t * lda + i] : 0.0;
             double sacc = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-            for (int t = 0; t < i; ++t) {
-                const double lit = (i < w && t < w) ? A[t * lda + i] : 0.0;
-                sacc -= lit * x[t];
-            }
+            for (int t = 0; t < i; ++t) sacc -= row[t] * x[t];
             x[i] = (i >= j) ? sacc : 0.0;
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) Li[i * 17 + j] = x[i];
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Out[i * 17 + j] = x[i];
 }
-
 // ------------------------------------------------------------------ helpers
 __global__ void k_zero(double *__restrict__ p, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -158,6 +157,169 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 //   3. the four waves update the R x R trailing entries with FP64 MFMA.
 // Pivot divisions are FP64 divisions; a zero or non-finite pivot records its
 // permuted column in info[0].
+// One column chunk of the chunked GETRF.  W = 16 is the full-width chunk
+// (every width guard folds away); W = 0 takes the width at run time (the
+// last chunk of a block).  Loads guarded per lane read a clamped, valid
+// address and select zero, so they are issued without branches.
+template <int W>
+__device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, int r0, const ChunkDev &C,
+                                                 const int *Rs, double *Ui, double *Li, double *work,
+                                                 unsigned long long *__restrict__ info, int wave, int lane,
+                                                 int tid) {
+    const int li = lane & 15, lk = lane >> 4;
+    const int c0 = C.c0, w = W ? W : C.w, nr = C.nr;
+    const int T = w + nr;
+    const int wu = w + 1;
+    double *Pn = work;                     // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
+    double *Uc = work + (size_t)T * w;     // Uc[s*wu + j]: U(c0 + j, Rs[s])
+    // one item per panel row (its w values) or per coupled column (its w
+    // values, contiguous in D): the loads of an item are issued together
+    for (int it = tid; it < T + nr; it += 256) {
+        double v[16];
+        if (it < T) {
+            const int row = it < w ? c0 + it : Rs[it - w];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = j < w ? D[row + (size_t)(c0 + j) * b] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < w) Pn[j * T + it] = v[j];
+        } else {
+            const int sI = it - T;
+            const double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = j < w ? col[j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < w) Uc[sI * wu + j] = v[j];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) lu16_wave0(Pn, T, w, lane, r0 + c0, info);
+    __syncthreads();
+    if (wave == 0) {
+        if (lane < w) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < w) D[c0 + lane + (size_t)(c0 + j) * b] = Pn[j * T + lane];
+        }
+    } else if (wave == 1) {
+        tri_inverse16(Pn, T, w, lane, true, Ui);
+    } else if (wave == 2) {
+        tri_inverse16(Pn, T, w, lane, false, Li);
+    }
+    __syncthreads();
+    // coupled rows and columns: 16 x 16 output tiles, four waves
+    const int nrt = (nr + 15) >> 4;
+    for (int q = wave; q < 2 * nrt; q += 4) {
+        double4_t acc = {0, 0, 0, 0};
+        if (q < nrt) {
+            // L rows, transposed: X^T = U^{-T} A_rows^T, output element
+            // (chunk column lk + 4r, coupled row 16q + li)
+            const int ar = 16 * q + li;
+            const bool va = ar < nr;
+            const int arc = va ? ar : nr - 1;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const double a = Ui[k * 17 + li];                            // (U^{-T})[li][k]
+                const double bl = Pn[(k < w ? k : 0) * T + w + arc];
+                const double bv = (k < w && va) ? bl : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+            }
+            if (va) {
+                const size_t row = (size_t)Rs[ar];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = lk + 4 * r;
+                    if (j < w) {
+                        Pn[j * T + w + ar] = acc[r];
+                        D[row + (size_t)(c0 + j) * b] = acc[r];
+                    }
+                }
+            }
+        } else {
+            // U columns, transposed: Y^T = A_cols^T L^{-T}, output element
+            // (coupled column 16q' + lk + 4r, chunk row li)
+            const int qq = q - nrt;
+            const int sc = 16 * qq + li;
+            const bool vs = sc < nr;
+            const int scc = vs ? sc : nr - 1;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const double al = Uc[scc * wu + (k < w ? k : 0)];
+                const double a = (k < w && vs) ? al : 0.0;                   // (A_cols^T)[li][k]
+                const double bv = Li[li * 17 + k];                            // (L^{-T})[k][li]
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s2 = 16 * qq + lk + 4 * r;
+                if (s2 < nr && li < w) {
+                    Uc[s2 * wu + li] = acc[r];
+                    D[c0 + li + (size_t)Rs[s2] * b] = acc[r];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // trailing update of the coupled rows x coupled columns: each wave
+    // loads all entries of up to eight of its 16 x 16 tiles, then applies the
+    // rank-w product on MFMA and stores them back.  Tiles are transposed:
+    // output element (coupled column 16tj + lk + 4r, coupled row 16ti + li),
+    // so the 16 lanes of a group read and write consecutive rows of a column.
+    const int ntl = nrt;
+    const int ntiles = ntl * ntl;
+    for (int q0 = wave; q0 < ntiles; q0 += 32) {
+        double4_t acc[8];
+        bool vr[8];
+        size_t rowo[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 4 * u;
+            const int qc = q < ntiles ? q : ntiles - 1;
+            const int ti = qc / ntl, tj = qc - ti * ntl;
+            const int ra = 16 * ti + li;
+            vr[u] = q < ntiles && ra < nr;
+            rowo[u] = (size_t)Rs[ra < nr ? ra : nr - 1];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int sc = 16 * tj + lk + 4 * r;
+                const double val = D[rowo[u] + (size_t)Rs[sc < nr ? sc : nr - 1] * b];
+                acc[u][r] = (vr[u] && sc < nr) ? val : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 4 * u;
+            if (q < ntiles) {
+                const int ti = q / ntl, tj = q - ti * ntl;
+                const int sc = 16 * tj + li;
+                const int ar = 16 * ti + li;
+                const int scc = sc < nr ? sc : nr - 1, arc = ar < nr ? ar : nr - 1;
+                const bool va = ar < nr, vcc = sc < nr;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    if (4 * kk < w) {
+                        const int kc = k < w ? k : 0;
+                        const double al = Uc[scc * wu + kc], bl = Pn[kc * T + w + arc];
+                        const double a = (k < w && vcc) ? -al : 0.0;   // (U^T)[sc][k]
+                        const double bv = (k < w && va) ? bl : 0.0;    // (L^T)[k][ar]
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int sc2 = 16 * tj + lk + 4 * r;
+                    if (vr[u] && sc2 < nr) D[rowo[u] + (size_t)Rs[sc2] * b] = acc[u][r];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict__ slab, const LevelDev &L,
                                                               const ChunkDev *__restrict__ chunks,
                                                               const int32_t *__restrict__ crows, double *lds,
@@ -165,7 +327,6 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
     double *__restrict__ D = slab + L.offD;
     const int b = L.b;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
     const int maxnr = L.pad;                    // largest coupled-row count of a chunk
     int *Rbuf0 = (int *)lds;                    // coupled rows of the current / next chunk
     int *Rbuf1 = Rbuf0 + maxnr;
@@ -179,152 +340,18 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
     __syncthreads();
     for (int ch = L.chunk_begin; ch < L.chunk_end; ++ch) {
         const ChunkDev C = chunks[ch];
-        const int c0 = C.c0, w = C.w, nr = C.nr;
         const int *Rs = ((ch - L.chunk_begin) & 1) ? Rbuf1 : Rbuf0;
         int *Rn = ((ch - L.chunk_begin) & 1) ? Rbuf0 : Rbuf1;
-        const int T = w + nr;
-        const int wu = w + 1;
-        double *Pn = work;                     // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
-        double *Uc = work + (size_t)T * w;     // Uc[s*wu + j]: U(c0 + j, Rs[s])
-        // one item per panel row (its w values) or per coupled column (its w
-        // values, contiguous in D): the loads of an item are issued together
-        for (int it = tid; it < T + nr; it += 256) {
-            double v[16];
-            if (it < T) {
-                const int row = it < w ? c0 + it : Rs[it - w];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) v[j] = j < w ? D[row + (size_t)(c0 + j) * b] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < w) Pn[j * T + it] = v[j];
-            } else {
-                const int sI = it - T;
-                const double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) v[j] = j < w ? col[j] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < w) Uc[sI * wu + j] = v[j];
-            }
-        }
-        __syncthreads();
-        if (wave == 0) {
-            lu16_wave0(Pn, T, w, lane, L.r0 + c0, info);
-        } else if (ch + 1 < L.chunk_end) {
-            // the other waves fetch the next chunk's coupled rows meanwhile
+        // the next chunk's coupled rows go to the other buffer; the step's
+        // first barrier orders them before their use
+        if (ch + 1 < L.chunk_end) {
             const ChunkDev Cn = chunks[ch + 1];
-            for (int q = tid - 64; q < Cn.nr; q += 192) Rn[q] = crows[Cn.roff + q];
+            for (int q = tid; q < Cn.nr; q += 256) Rn[q] = crows[Cn.roff + q];
         }
-        __syncthreads();
-        if (wave == 0) {
-            tri_inverses16_wave0(Pn, T, w, lane, Ui, Li);
-            if (lane < w) {
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < w) D[c0 + lane + (size_t)(c0 + j) * b] = Pn[j * T + lane];
-            }
-        }
-        __syncthreads();
-        // coupled rows and columns: 16 x 16 output tiles, four waves
-        const int nrt = (nr + 15) >> 4;
-        for (int q = wave; q < 2 * nrt; q += 4) {
-            double4_t acc = {0, 0, 0, 0};
-            if (q < nrt) {
-                // L rows, transposed: X^T = U^{-T} A_rows^T, output element
-                // (chunk column lk + 4r, coupled row 16q + li)
-                const int ar = 16 * q + li;
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = 4 * kk + lk;
-                    const double a = Ui[k * 17 + li];                       // (U^{-T})[li][k]
-                    const double bv = (k < w && ar < nr) ? Pn[k * T + w + ar] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
-                }
-                if (ar < nr) {
-                    const size_t row = (size_t)Rs[ar];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int j = lk + 4 * r;
-                        if (j < w) {
-                            Pn[j * T + w + ar] = acc[r];
-                            D[row + (size_t)(c0 + j) * b] = acc[r];
-                        }
-                    }
-                }
-            } else {
-                // U columns, transposed: Y^T = A_cols^T L^{-T}, output element
-                // (coupled column 16q' + lk + 4r, chunk row li)
-                const int qq = q - nrt;
-                const int sc = 16 * qq + li;
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = 4 * kk + lk;
-                    const double a = (k < w && sc < nr) ? Uc[sc * wu + k] : 0.0;   // (A_cols^T)[li][k]
-                    const double bv = Li[li * 17 + k];                                // (L^{-T})[k][li]
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int s2 = 16 * qq + lk + 4 * r;
-                    if (s2 < nr && li < w) {
-                        Uc[s2 * wu + li] = acc[r];
-                        D[c0 + li + (size_t)Rs[s2] * b] = acc[r];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // trailing update of the coupled rows x coupled columns: each wave
-        // loads all entries of up to eight of its 16 x 16 tiles, then applies
-        // the rank-w product on MFMA and stores them back
-        const int ntl = nrt;
-        const int ntiles = ntl * ntl;
-        for (int q0 = wave; q0 < ntiles; q0 += 32) {
-            double4_t acc[8];
-            bool vc[8];
-            // transposed tiles: output element (coupled column 16tj + lk + 4r,
-            // coupled row 16ti + li), so the 16 lanes of a group read and
-            // write consecutive rows of one column of D
-            size_t rowo[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int q = q0 + 4 * u;
-                const int ti = q / ntl, tj = q - ti * ntl;
-                const int ra = 16 * ti + li;
-                vc[u] = q < ntiles && ra < nr;
-                rowo[u] = vc[u] ? (size_t)Rs[ra] : 0;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int sc = 16 * tj + lk + 4 * r;
-                    acc[u][r] = (vc[u] && sc < nr) ? D[rowo[u] + (size_t)Rs[sc] * b] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int q = q0 + 4 * u;
-                if (q < ntiles) {
-                    const int ti = q / ntl, tj = q - ti * ntl;
-                    const int sc = 16 * tj + li;
-                    const int ar = 16 * ti + li;
-                    const bool va = ar < nr, vcc = sc < nr;
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int k = 4 * kk + lk;
-                        if (4 * kk < w) {
-                            const double a = (k < w && vcc) ? -Uc[sc * wu + k] : 0.0;   // (U^T)[sc][k]
-                            const double bv = (k < w && va) ? Pn[k * T + w + ar] : 0.0;  // (L^T)[k][ar]
-                            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
-                        }
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int sc2 = 16 * tj + lk + 4 * r;
-                        if (vc[u] && sc2 < nr) D[rowo[u] + (size_t)Rs[sc2] * b] = acc[u][r];
-                    }
-                }
-            }
-        }
-        __syncthreads();
+        if (C.w == 16)
+            getrf_chunk_step<16>(D, b, L.r0, C, Rs, Ui, Li, work, info, wave, lane, tid);
+        else
+            getrf_chunk_step<0>(D, b, L.r0, C, Rs, Ui, Li, work, info, wave, lane, tid);
     }
 }
 

@@ -172,6 +172,36 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     const int wu = w + 1;
     double *Pn = work;                     // Pn[j*T + t]: chunk column j, panel row t (t < w: chunk rows)
     double *Uc = work + (size_t)T * w;     // Uc[s*wu + j]: U(c0 + j, Rs[s])
+    const int nrt = (nr + 15) >> 4;
+    const int ntl = nrt;
+    const int ntiles = ntl * ntl;
+    // Trailing tiles are transposed 16 x 16 tiles of the coupled rows x
+    // coupled columns: output element (coupled column 16tj + lk + 4r,
+    // coupled row 16ti + li), so the 16 lanes of a group read and write
+    // consecutive rows of a column.  A wave takes up to eight tiles per round.
+    double4_t acc[8];
+    bool vr[8];
+    size_t rowo[8];
+    auto load_tiles = [&](int q0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 4 * u;
+            const int qc = q < ntiles ? q : ntiles - 1;
+            const int ti = qc / ntl, tj = qc - ti * ntl;
+            const int ra = 16 * ti + li;
+            vr[u] = q < ntiles && ra < nr;
+            rowo[u] = (size_t)Rs[ra < nr ? ra : nr - 1];
+            // entries outside the coupled set read a clamped valid address;
+            // an MFMA output element depends only on its own accumulator
+            // input and those elements are never stored, so no select is
+            // needed (it would make each load wait at once)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int sc = 16 * tj + lk + 4 * r;
+                acc[u][r] = D[rowo[u] + (size_t)Rs[sc < nr ? sc : nr - 1] * b];
+            }
+        }
+    };
     // one item per panel row (its w values) or per coupled column (its w
     // values, contiguous in D): the loads of an item are issued together
     for (int it = tid; it < T + nr; it += 256) {
@@ -193,6 +223,11 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 if (j < w) Uc[sI * wu + j] = v[j];
         }
     }
+    // The coupled rows x coupled columns entries are not touched by steps
+    // 1 and 2, so the first round of trailing tiles is loaded now and its
+    // latency overlaps the diagonal LU, the inverses and the solves.  (A
+    // barrier waits for LDS traffic only; these loads stay in flight.)
+    if (nr > 0) load_tiles(wave);
     __syncthreads();
     if (wave == 0) lu16_wave0(Pn, T, w, lane, r0 + c0, info);
     __syncthreads();
@@ -209,9 +244,8 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     }
     __syncthreads();
     // coupled rows and columns: 16 x 16 output tiles, four waves
-    const int nrt = (nr + 15) >> 4;
     for (int q = wave; q < 2 * nrt; q += 4) {
-        double4_t acc = {0, 0, 0, 0};
+        double4_t sacc = {0, 0, 0, 0};
         if (q < nrt) {
             // L rows, transposed: X^T = U^{-T} A_rows^T, output element
             // (chunk column lk + 4r, coupled row 16q + li)
@@ -224,7 +258,7 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 const double a = Ui[k * 17 + li];                            // (U^{-T})[li][k]
                 const double bl = Pn[(k < w ? k : 0) * T + w + arc];
                 const double bv = (k < w && va) ? bl : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+                sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, sacc, 0, 0, 0);
             }
             if (va) {
                 const size_t row = (size_t)Rs[ar];
@@ -232,8 +266,8 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 for (int r = 0; r < 4; ++r) {
                     const int j = lk + 4 * r;
                     if (j < w) {
-                        Pn[j * T + w + ar] = acc[r];
-                        D[row + (size_t)(c0 + j) * b] = acc[r];
+                        Pn[j * T + w + ar] = sacc[r];
+                        D[row + (size_t)(c0 + j) * b] = sacc[r];
                     }
                 }
             }
@@ -250,45 +284,23 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 const double al = Uc[scc * wu + (k < w ? k : 0)];
                 const double a = (k < w && vs) ? al : 0.0;                   // (A_cols^T)[li][k]
                 const double bv = Li[li * 17 + k];                            // (L^{-T})[k][li]
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+                sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, sacc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int s2 = 16 * qq + lk + 4 * r;
                 if (s2 < nr && li < w) {
-                    Uc[s2 * wu + li] = acc[r];
-                    D[c0 + li + (size_t)Rs[s2] * b] = acc[r];
+                    Uc[s2 * wu + li] = sacc[r];
+                    D[c0 + li + (size_t)Rs[s2] * b] = sacc[r];
                 }
             }
         }
     }
     __syncthreads();
-    // trailing update of the coupled rows x coupled columns: each wave
-    // loads all entries of up to eight of its 16 x 16 tiles, then applies the
-    // rank-w product on MFMA and stores them back.  Tiles are transposed:
-    // output element (coupled column 16tj + lk + 4r, coupled row 16ti + li),
-    // so the 16 lanes of a group read and write consecutive rows of a column.
-    const int ntl = nrt;
-    const int ntiles = ntl * ntl;
+    // trailing update of the coupled rows x coupled columns: the rank-w
+    // product on MFMA applied to each wave's loaded tiles, stored back
     for (int q0 = wave; q0 < ntiles; q0 += 32) {
-        double4_t acc[8];
-        bool vr[8];
-        size_t rowo[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 4 * u;
-            const int qc = q < ntiles ? q : ntiles - 1;
-            const int ti = qc / ntl, tj = qc - ti * ntl;
-            const int ra = 16 * ti + li;
-            vr[u] = q < ntiles && ra < nr;
-            rowo[u] = (size_t)Rs[ra < nr ? ra : nr - 1];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int sc = 16 * tj + lk + 4 * r;
-                const double val = D[rowo[u] + (size_t)Rs[sc < nr ? sc : nr - 1] * b];
-                acc[u][r] = (vr[u] && sc < nr) ? val : 0.0;
-            }
-        }
+        if (q0 != wave) load_tiles(q0);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int q = q0 + 4 * u;
@@ -619,16 +631,19 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
         // column t of the row block is RT contiguous doubles of X
         for (int t0 = tid / RT; t0 < kp; t0 += 8 * (256 / RT)) {
             const int r = tid % RT;
+            // unconditional loads from clamped addresses, issued together;
+            // the padding is zeroed when the values are stored to LDS
+            const int rc = r < nrow ? r : nrow - 1;
             double v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int t = t0 + u * (256 / RT);
-                v[u] = (r < nrow && t < kap) ? X[a0 + r + (size_t)t * m] : 0.0;
+                v[u] = X[a0 + rc + (size_t)(t < kap ? t : kap - 1) * m];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int t = t0 + u * (256 / RT);
-                if (t < kp) xs_lds[t * LD + r] = v[u];
+                if (t < kp) xs_lds[t * LD + r] = (r < nrow && t < kap) ? v[u] : 0.0;
             }
         }
         __syncthreads();

@@ -339,10 +339,17 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             L.seg_end = (int32_t)an.segs.size();
             L.offD = off;
             off += align32((int64_t)L.b * L.b);
+            // P_i and Qt_i keep kappa rounded up to 16 columns; the padding
+            // columns stay zero, so GEMM operand loads need no masking
+            const int64_t kpad = (int64_t)(L.kappa + 15) / 16 * 16;
             L.offP = off;
-            off += align32((int64_t)L.m * L.kappa);
+            off += align32((int64_t)L.m * kpad);
             L.offQ = off;
-            off += align32((int64_t)L.m * L.kappa);
+            off += align32((int64_t)L.m * kpad);
+            for (size_t a = 0, sgi = 0; a < rows.size(); ++a) {
+                while (an.segs[L.seg_begin + sgi].start + an.segs[L.seg_begin + sgi].len <= (int32_t)a) ++sgi;
+                an.R_seg.push_back((int32_t)sgi);
+            }
             an.max_gemm_k = std::max(an.max_gemm_k, kap);
         }
     }
@@ -460,69 +467,70 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         an.tri_doubles = toff;
     }
 
-    // SSSSM tasks and maps
+    // SSSSM: every pair (sa, sb) of segments of level i is a target
+    // block (k, j) (sa-major order in stgt).  Product element (a, b), with a
+    // in segment sa and b in segment sb, lands at
+    //     stgt[task_begin + sa * nseg + sb] + RO[sb][a] + CO[sa][b]
+    // where RO[sb] (m entries at maps[moff + sb * m]) and CO[sa] (m entries
+    // at maps[moff + (nseg + sa) * m]) are the row / column offsets inside
+    // the target, -1 where S has no entry there.
     for (int64_t i = 0; i < p; ++i) {
         LevelDev &L = an.levels[i];
-        L.task_begin = (int64_t)an.tasks.size();
-        L.tile_begin = (int64_t)an.tiles.size();
+        L.task_begin = (int64_t)an.stgt.size();
+        L.moff = (int64_t)an.maps.size();
         const int32_t *rows_i = an.R_idx.data() + L.Roff;
+        const int32_t nseg = L.seg_end - L.seg_begin;
         if (L.kappa > 0) {
             an.stored_flops += 2.0 * 2.0 * (double)L.m * L.kappa * L.kappa / 2.0;
-            for (int32_t sa = L.seg_begin; sa < L.seg_end; ++sa) {
-                const Segment A = an.segs[sa];
+            an.stored_flops += 2.0 * (double)L.m * L.m * L.kappa;
+            an.maps.resize(an.maps.size() + 2 * (size_t)nseg * L.m, -1);
+            int32_t *RO = an.maps.data() + L.moff;
+            int32_t *CO = RO + (size_t)nseg * L.m;
+            for (int32_t sa = 0; sa < nseg; ++sa) {
+                const Segment A = an.segs[L.seg_begin + sa];
                 const int32_t k = A.blk;
                 const LevelDev &Lk = an.levels[k];
-                for (int32_t sb = L.seg_begin; sb < L.seg_end; ++sb) {
-                    const Segment B = an.segs[sb];
+                for (int32_t sb = 0; sb < nseg; ++sb) {
+                    const Segment B = an.segs[L.seg_begin + sb];
                     const int32_t j = B.blk;
                     const LevelDev &Lj = an.levels[j];
-                    TaskDev t{};
-                    t.a0 = A.start;
-                    t.alen = A.len;
-                    t.b0 = B.start;
-                    t.blen = B.len;
-                    t.rmap = (int64_t)an.maps.size();
+                    int32_t *ro = RO + (size_t)sb * L.m + A.start;   // rows of segment sa
+                    int32_t *co = CO + (size_t)sa * L.m + B.start;   // columns of segment sb
+                    int64_t tgt;
                     if (k == j) {
-                        t.tgt = Lk.offD;
-                        t.rs = 1;
-                        t.cs = Lk.b;
-                        for (int32_t a = 0; a < A.len; ++a) an.maps.push_back(rows_i[A.start + a] - Lk.r0);
-                        t.cmap = (int64_t)an.maps.size();
-                        for (int32_t c = 0; c < B.len; ++c) an.maps.push_back(rows_i[B.start + c] - Lk.r0);
-                    } else if (k > j) {
-                        // L block (k, j) inside P_j: row = position in rows_j, col = position in K_j
-                        t.tgt = Lj.offP;
-                        t.rs = 1;
-                        t.cs = Lj.m;
-                        const int32_t *rows_j = an.R_idx.data() + Lj.Roff;
-                        for (int32_t a = 0; a < A.len; ++a)
-                            an.maps.push_back(lower_pos(rows_j, Lj.m, rows_i[A.start + a]));
-                        t.cmap = (int64_t)an.maps.size();
-                        for (int32_t c = 0; c < B.len; ++c) an.maps.push_back(an.posK[rows_i[B.start + c]]);
-                    } else {
-                        // U block (k, j) inside Qt_k: Qt_k[pos in rows_k, pos in K_k]
-                        t.tgt = Lk.offQ;
-                        t.rs = Lk.m;
-                        t.cs = 1;
-                        const int32_t *rows_k = an.R_idx.data() + Lk.Roff;
-                        for (int32_t a = 0; a < A.len; ++a) an.maps.push_back(an.posK[rows_i[A.start + a]]);
-                        t.cmap = (int64_t)an.maps.size();
+                        // diagonal block D_k, column-major
+                        tgt = Lk.offD;
+                        for (int32_t a = 0; a < A.len; ++a) ro[a] = rows_i[A.start + a] - Lk.r0;
                         for (int32_t c = 0; c < B.len; ++c)
-                            an.maps.push_back(lower_pos(rows_k, Lk.m, rows_i[B.start + c]));
+                            co[c] = (rows_i[B.start + c] - Lk.r0) * Lk.b;
+                    } else if (k > j) {
+                        // L block (k, j) inside P_j: row = position in rows_j, column = position in K_j
+                        tgt = Lj.offP;
+                        const int32_t *rows_j = an.R_idx.data() + Lj.Roff;
+                        for (int32_t a = 0; a < A.len; ++a) ro[a] = lower_pos(rows_j, Lj.m, rows_i[A.start + a]);
+                        for (int32_t c = 0; c < B.len; ++c) {
+                            const int64_t t = an.posK[rows_i[B.start + c]];
+                            if (t >= 0 && t * Lj.m >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
+                            co[c] = t < 0 ? -1 : (int32_t)(t * Lj.m);
+                        }
+                    } else {
+                        // U block (k, j) inside Qt_k: Qt_k[position in rows_k, position in K_k]
+                        tgt = Lk.offQ;
+                        const int32_t *rows_k = an.R_idx.data() + Lk.Roff;
+                        for (int32_t a = 0; a < A.len; ++a) {
+                            const int64_t t = an.posK[rows_i[A.start + a]];
+                            if (t >= 0 && t * Lk.m >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
+                            ro[a] = t < 0 ? -1 : (int32_t)(t * Lk.m);
+                        }
+                        for (int32_t c = 0; c < B.len; ++c) co[c] = lower_pos(rows_k, Lk.m, rows_i[B.start + c]);
                     }
-                    const int32_t task_id = (int32_t)an.tasks.size();
-                    an.tasks.push_back(t);
-                    const int32_t nti = (A.len + kTile - 1) / kTile, ntj = (B.len + kTile - 1) / kTile;
-                    for (int32_t ti = 0; ti < nti; ++ti)
-                        for (int32_t tj = 0; tj < ntj; ++tj) an.tiles.push_back(TileDev{task_id, (ti << 16) | tj});
-                    an.stored_flops += 2.0 * (double)nti * kTile * ntj * kTile * L.kappa;
+                    an.stgt.push_back(tgt);
                 }
             }
         }
-        L.task_end = (int64_t)an.tasks.size();
-        L.tile_end = (int64_t)an.tiles.size();
+        L.task_end = (int64_t)an.stgt.size();
     }
-    if ((int64_t)an.tasks.size() >= ((int64_t)1 << 31) || an.maps.size() >= ((size_t)1 << 40))
+    if ((int64_t)an.stgt.size() >= ((int64_t)1 << 31) || an.maps.size() >= ((size_t)1 << 40))
         return SLU_ERR_LIMIT;
 
     // schedule: waves of levels with equal height in the dependency tree of
@@ -591,16 +599,24 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             an.slot[q] = s;
         }
     }
-    // every map entry must address inside its target array
+    // every product element must address inside the slab
     for (int64_t i = 0; i < p; ++i) {
         const LevelDev &L = an.levels[i];
-        for (int64_t t = L.task_begin; t < L.task_end; ++t) {
-            const TaskDev &T = an.tasks[t];
-            int64_t rmax = -1, cmax = -1;
-            for (int32_t a = 0; a < T.alen; ++a) rmax = std::max<int64_t>(rmax, an.maps[T.rmap + a]);
-            for (int32_t c = 0; c < T.blen; ++c) cmax = std::max<int64_t>(cmax, an.maps[T.cmap + c]);
-            const int64_t last = T.tgt + std::max<int64_t>(rmax, 0) * T.rs + std::max<int64_t>(cmax, 0) * T.cs;
-            if (last >= an.slab_doubles || T.a0 + T.alen > L.m || T.b0 + T.blen > L.m) return SLU_ERR_LIMIT;
+        const int32_t nseg = L.seg_end - L.seg_begin;
+        if (L.task_end - L.task_begin != (L.kappa > 0 ? (int64_t)nseg * nseg : 0)) return SLU_ERR_LIMIT;
+        if (L.kappa == 0) continue;
+        const int32_t *RO = an.maps.data() + L.moff;
+        const int32_t *CO = RO + (size_t)nseg * L.m;
+        for (int32_t sa = 0; sa < nseg; ++sa) {
+            const Segment A = an.segs[L.seg_begin + sa];
+            for (int32_t sb = 0; sb < nseg; ++sb) {
+                const Segment B = an.segs[L.seg_begin + sb];
+                int64_t rmax = 0, cmax = 0;
+                for (int32_t a = 0; a < A.len; ++a) rmax = std::max<int64_t>(rmax, RO[(size_t)sb * L.m + A.start + a]);
+                for (int32_t c = 0; c < B.len; ++c) cmax = std::max<int64_t>(cmax, CO[(size_t)sa * L.m + B.start + c]);
+                if (an.stgt[L.task_begin + (int64_t)sa * nseg + sb] + rmax + cmax >= an.slab_doubles)
+                    return SLU_ERR_LIMIT;
+            }
         }
     }
     (void)nnzL;

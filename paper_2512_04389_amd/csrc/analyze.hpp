@@ -20,6 +20,7 @@ namespace slu {
 // symmetric, the U blocks to the right of D_i couple the same index sets.
 //   P_i  (m x kappa, column-major, ld = m):  P_i[a, t]  = L(rows_i[a], r0 + K_i[t])
 //   Qt_i (m x kappa, column-major, ld = m):  Qt_i[a, t] = U(r0 + K_i[t], rows_i[a])
+// Both are followed by zero columns up to kappa rounded to 16.
 // rows_i is cut into segments, one per target block row k > i.
 //
 // The panel solves use compact copies of the coupled triangles in the "tri"
@@ -33,8 +34,8 @@ struct LevelDev {
     int64_t offD, offP, offQ;   // slab offsets in doubles
     int64_t offT;               // tri region offset in doubles
     int64_t Koff, Roff;         // offsets into K_idx / R_idx
-    int64_t task_begin, task_end;
-    int64_t tile_begin, tile_end;
+    int64_t task_begin, task_end;   // segment pairs (SSSSM targets) in stgt, sa-major
+    int64_t moff;                   // SSSSM offset tables in maps
     int32_t r0, b, kappa, m;
     int32_t chunk_begin, chunk_end;
     int32_t seg_begin, seg_end;
@@ -51,16 +52,6 @@ struct ChunkDev {
     int64_t roff;               // offset into chunk_rows
 };
 
-// One SSSSM target (k, j) of level i:  B_kj -= P_i[a0:a0+alen, :] * Qt_i[b0:b0+blen, :]^T
-// The product element (a, b) lands at  tgt + rowmap[a]*rs + colmap[b]*cs
-// unless a map entry is -1 (the product is structurally zero there).
-struct TaskDev {
-    int64_t tgt;
-    int64_t rmap, cmap;         // offsets into maps
-    int32_t rs, cs;
-    int32_t a0, alen, b0, blen;
-};
-
 // Levels that run together: equal height in the block dependency tree
 // (parent of block i = the first block below it coupled to it).  Launch
 // parameters are the maxima over the wave's levels.
@@ -71,12 +62,6 @@ struct WaveInfo {
     int32_t max_m;              // largest panel row count
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
-};
-
-// Output tile (32 x 32) of one SSSSM task.
-struct TileDev {
-    int32_t task;
-    int32_t tij;                // (ti << 16) | tj
 };
 
 struct Segment {
@@ -102,9 +87,9 @@ struct Analysis {
     std::vector<Segment> segs;
     std::vector<ChunkDev> chunks;
     std::vector<int32_t> chunk_rows; // local rows
-    std::vector<TaskDev> tasks;
-    std::vector<int32_t> maps;
-    std::vector<TileDev> tiles;
+    std::vector<int32_t> R_seg;      // segment (local index) of every row of R_idx
+    std::vector<int64_t> stgt;       // SSSSM target base offset per segment pair
+    std::vector<int32_t> maps;       // SSSSM row / column offset tables
     std::vector<WaveInfo> waves;
     std::vector<int32_t> wave_levels;
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
@@ -122,8 +107,8 @@ struct Analysis {
     int32_t max_gemm_k = 0;
 };
 
-// Tile edge of the SSSSM output tiles.
-constexpr int kTile = 32;
+// Tile edge of the SSSSM output tiles (one workgroup each).
+constexpr int kSsssmTile = 64;
 // Largest diagonal block factored in one LDS-resident chunk.
 constexpr int kLdsDenseMax = 128;
 // LDS budget of the chunked GETRF (bytes).

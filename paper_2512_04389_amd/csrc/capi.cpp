@@ -16,7 +16,7 @@ struct slu_handle {
     void *ws = nullptr;
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
-    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_tasks, o_maps, o_tiles, o_slot, o_arow, o_acol,
+    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
         o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_norms;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
@@ -53,9 +53,9 @@ void plan_workspace(slu_handle *h) {
     h->o_R = take(an.R_idx.size() * 4);
     h->o_chunks = take(an.chunks.size() * sizeof(slu::ChunkDev));
     h->o_crows = take(an.chunk_rows.size() * 4);
-    h->o_tasks = take(an.tasks.size() * sizeof(slu::TaskDev));
+    h->o_rseg = take(an.R_seg.size() * 4);
+    h->o_stgt = take(an.stgt.size() * 8);
     h->o_maps = take(an.maps.size() * 4);
-    h->o_tiles = take(an.tiles.size() * sizeof(slu::TileDev));
     h->o_slot = take(an.slot.size() * 8);
     h->o_arow = take(an.a_rowptr.size() * 8);
     h->o_acol = take(an.a_colidx.size() * 4);
@@ -194,9 +194,9 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_R, an.R_idx, s);
     if (e == hipSuccess) e = upload(base, h->o_chunks, an.chunks, s);
     if (e == hipSuccess) e = upload(base, h->o_crows, an.chunk_rows, s);
-    if (e == hipSuccess) e = upload(base, h->o_tasks, an.tasks, s);
+    if (e == hipSuccess) e = upload(base, h->o_rseg, an.R_seg, s);
+    if (e == hipSuccess) e = upload(base, h->o_stgt, an.stgt, s);
     if (e == hipSuccess) e = upload(base, h->o_maps, an.maps, s);
-    if (e == hipSuccess) e = upload(base, h->o_tiles, an.tiles, s);
     if (e == hipSuccess) e = upload(base, h->o_slot, an.slot, s);
     if (e == hipSuccess) e = upload(base, h->o_arow, an.a_rowptr, s);
     if (e == hipSuccess) e = upload(base, h->o_acol, an.a_colidx, s);
@@ -217,9 +217,9 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.R_idx = (const int32_t *)(base + h->o_R);
     d.chunks = (const slu::ChunkDev *)(base + h->o_chunks);
     d.chunk_rows = (const int32_t *)(base + h->o_crows);
-    d.tasks = (const slu::TaskDev *)(base + h->o_tasks);
+    d.rseg = (const int32_t *)(base + h->o_rseg);
+    d.stgt = (const int64_t *)(base + h->o_stgt);
     d.maps = (const int32_t *)(base + h->o_maps);
-    d.tiles = (const slu::TileDev *)(base + h->o_tiles);
     d.slot = (const int64_t *)(base + h->o_slot);
     d.a_rowptr = (const int64_t *)(base + h->o_arow);
     d.a_colidx = (const int32_t *)(base + h->o_acol);
@@ -314,7 +314,7 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
             const int i = an.wave_levels[q];
             const slu::LevelDev &L = an.levels[i];
             if (L.kappa > 0)
-                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.tile_end - L.tile_begin, s));
+                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.m, s));
         }
     }
 #undef SLU_TIMED
@@ -371,7 +371,7 @@ int slu_get_info(const slu_handle *h, slu_info *info) {
     info->nnz_s = 2 * (an.s_colptr.empty() ? 0 : an.s_colptr[an.n]) - an.n;
     info->nblocks = an.p;
     info->nonempty_blocks = an.nonempty_blocks;
-    info->ssssm_tasks = (int64_t)an.tasks.size();
+    info->ssssm_tasks = (int64_t)an.stgt.size();
     info->flops = an.flops;
     info->flops_getrf = an.flops_getrf;
     info->flops_panel = an.flops_panel;

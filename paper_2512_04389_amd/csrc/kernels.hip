@@ -714,100 +714,139 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
 }
 
 // --------------------------------------------------------------------- SSSSM
-// Alg. 1 "B_kj <- B_kj - B_ki B_ij" for every target (k, j) of level i: the
-// product P_i[a-segment] * Qt_i[b-segment]^T over the coupled index set,
-// on FP64 MFMA (v_mfma_f64_16x16x4f64).  One wave computes a 32 x 32 output
-// tile as 2 x 2 MFMA blocks and subtracts it from the target through the
-// task's row / column maps.  Targets are distinct within a level, so the
-// stores never collide.
+// Alg. 1 "B_kj <- B_kj - B_ki B_ij" for every target (k, j) of level i in one
+// launch: the product C = P_i Qt_i^T (m x m, inner dimension kappa) on FP64
+// MFMA (v_mfma_f64_16x16x4f64), tiled 64 x 64 over the whole m x m range
+// regardless of segment boundaries.  One workgroup per tile, four waves of
+// 32 x 32 (2 x 2 MFMA blocks each); both operands are staged through LDS 16
+// inner indices at a time, double-buffered, the next slice's global loads in
+// flight during the current slice's MFMAs.  Element (a, b) of C belongs to
+// the target of segment pair (seg(a), seg(b)) and is subtracted at
+//     stgt[seg(a) * nseg + seg(b)] + RO[seg(b)][a] + CO[seg(a)][b]
+// unless an offset is -1 (S has no entry there).  Targets are distinct
+// within a level, so the stores never collide.
 //
 // MFMA f64 16x16x4 operand layout (lane l): A[i][k] with i = l % 16,
 // k = l / 16; B[k][j] with j = l % 16, k = l / 16; result element r of lane l
 // is D[l / 16 + 4 * r][l % 16] (checked on gfx950 with a lane-layout probe).
-__global__ __launch_bounds__(64) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                              int level, const TaskDev *__restrict__ tasks,
-                                              const int32_t *__restrict__ maps,
-                                              const TileDev *__restrict__ tiles) {
+constexpr int kSsKC = 16;               // inner indices per LDS slice
+constexpr int kSsLd = kSsssmTile + 4;   // LDS row stride (doubles)
+
+__global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                               int level, const int32_t *__restrict__ rseg,
+                                               const int64_t *__restrict__ stgt,
+                                               const int32_t *__restrict__ maps) {
+    __shared__ double As[2][kSsKC][kSsLd], Bs[2][kSsKC][kSsLd];
     const LevelDev L = levels[level];
-    const TileDev tl = tiles[L.tile_begin + blockIdx.x];
-    const TaskDev T = tasks[tl.task];
-    const int ti = tl.tij >> 16, tj = tl.tij & 0xffff;
-    const double *__restrict__ P = slab + L.offP;
-    const double *__restrict__ Q = slab + L.offQ;
-    const int m = L.m, kap = L.kappa;
-    const int lane = threadIdx.x;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int ar0 = ti * 32 + lr, ar1 = ar0 + 16;
-    const int bc0 = tj * 32 + lr, bc1 = bc0 + 16;
-    const bool va0 = ar0 < T.alen, va1 = ar1 < T.alen, vb0 = bc0 < T.blen, vb1 = bc1 < T.blen;
-    const double *__restrict__ pa0 = P + T.a0 + ar0;
-    const double *__restrict__ pa1 = P + T.a0 + ar1;
-    const double *__restrict__ qb0 = Q + T.b0 + bc0;
-    const double *__restrict__ qb1 = Q + T.b0 + bc1;
-    double4_t c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-    // operands of 4 k-steps (16 inner indices) are loaded together, one
-    // group ahead of the MFMAs that consume them
-    constexpr int G = 4;
-    double a0[G], a1[G], b0[G], b1[G];
-    auto load_group = [&](int kg) {
+    const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
+    const int nt = (m + kSsssmTile - 1) / kSsssmTile;
+    const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wr = wave >> 1, wc = wave & 1;
+
+    // epilogue addressing, loaded first so that its latency overlaps the
+    // products: this lane's 8 rows a and 2 columns b of the tile
+    const int32_t *__restrict__ RS = rseg + L.Roff;
+    const int32_t *__restrict__ RO = maps + L.moff;
+    const int32_t *__restrict__ CO = RO + (size_t)nseg * m;
+    const int64_t *__restrict__ TG = stgt + L.task_begin;
+    int rowa[2][4], colb[2], sa[2][4], sb[2];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int k = kg + 4 * g + lk;
-            const bool vk = k < kap;
-            const size_t ko = (size_t)k * m;
-            a0[g] = (va0 && vk) ? pa0[ko] : 0.0;
-            a1[g] = (va1 && vk) ? pa1[ko] : 0.0;
-            b0[g] = (vb0 && vk) ? qb0[ko] : 0.0;
-            b1[g] = (vb1 && vk) ? qb1[ko] : 0.0;
-        }
-    };
-    load_group(0);
-    for (int kg = 0; kg < kap; kg += 4 * G) {
-        double ca0[G], ca1[G], cb0[G], cb1[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            ca0[g] = a0[g];
-            ca1[g] = a1[g];
-            cb0[g] = b0[g];
-            cb1[g] = b1[g];
-        }
-        if (kg + 4 * G < kap) load_group(kg + 4 * G);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[g], cb0[g], c00, 0, 0, 0);
-            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[g], cb1[g], c01, 0, 0, 0);
-            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[g], cb0[g], c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[g], cb1[g], c11, 0, 0, 0);
-        }
+    for (int bj = 0; bj < 2; ++bj) {
+        colb[bj] = tj * kSsssmTile + wc * 32 + bj * 16 + li;
+        sb[bj] = RS[min(colb[bj], m - 1)];
     }
-    const int32_t *__restrict__ rmap = maps + T.rmap;
-    const int32_t *__restrict__ cmap = maps + T.cmap;
-    double *__restrict__ tgt = slab + T.tgt;
-    const double4_t acc[2][2] = {{c00, c01}, {c10, c11}};
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int bcol = tj * 32 + bj * 16 + lr;
-            if (bcol >= T.blen) continue;
-            const int cp = cmap[bcol];
-            if (cp < 0) continue;
+        for (int r = 0; r < 4; ++r) {
+            rowa[bi][r] = ti * kSsssmTile + wr * 32 + bi * 16 + lk + 4 * r;
+            sa[bi][r] = RS[min(rowa[bi][r], m - 1)];
+        }
+    int ro[2][2][4], co[2][2][4];
+    int64_t tg[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int a = ti * 32 + bi * 16 + lk + 4 * r;
-                if (a >= T.alen) continue;
-                const int rp = rmap[a];
-                if (rp < 0) continue;
-                tgt[(int64_t)rp * T.rs + (int64_t)cp * T.cs] -= acc[bi][bj][r];
+                ro[bi][bj][r] = RO[(size_t)sb[bj] * m + min(rowa[bi][r], m - 1)];
+                co[bi][bj][r] = CO[(size_t)sa[bi][r] * m + min(colb[bj], m - 1)];
+                tg[bi][bj][r] = TG[sa[bi][r] * nseg + sb[bj]];
             }
+
+    // operand staging: thread (row lr, inner kq) moves P / Qt entries
+    // (row, k0 + kq + 4u), u < 4; rows past m read row m - 1 (never stored)
+    const int lr = tid & 63, kq = tid >> 6;
+    const double *__restrict__ pp = slab + L.offP + min(ti * kSsssmTile + lr, m - 1) + (size_t)kq * m;
+    const double *__restrict__ qp = slab + L.offQ + min(tj * kSsssmTile + lr, m - 1) + (size_t)kq * m;
+    double ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ra[u] = pp[(size_t)(k0 + 4 * u) * m];
+            rb[u] = qp[(size_t)(k0 + 4 * u) * m];
         }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[buf][kq + 4 * u][lr] = ra[u];
+            Bs[buf][kq + 4 * u][lr] = rb[u];
+        }
+    };
+    double4_t c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+    const int nch = kp / kSsKC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload((c + 1) * kSsKC);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + lk;
+            const double a0 = As[buf][k][wr * 32 + li], a1 = As[buf][k][wr * 32 + 16 + li];
+            const double b0 = Bs[buf][k][wc * 32 + li], b1 = Bs[buf][k][wc * 32 + 16 + li];
+            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+        }
+        if (c + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
     }
+
+    // subtract from the targets: all loads first, then the stores
+    const double4_t acc[2][2] = {{c00, c01}, {c10, c11}};
+    int64_t off[2][2][4];
+    double tv[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool ok = rowa[bi][r] < m && colb[bj] < m && ro[bi][bj][r] >= 0 && co[bi][bj][r] >= 0;
+                off[bi][bj][r] = ok ? tg[bi][bj][r] + ro[bi][bj][r] + co[bi][bj][r] : -1;
+                tv[bi][bj][r] = slab[ok ? off[bi][bj][r] : 0];
+            }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - acc[bi][bj][r];
 }
 
-hipError_t launch_ssssm(const DevPlan &d, int level, int64_t ntiles, hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ssssm, dim3((unsigned)ntiles), dim3(64), 0, s, d.slab, d.levels, level, d.tasks, d.maps,
-                       d.tiles);
+hipError_t launch_ssssm(const DevPlan &d, int level, int m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const int nt = (m + kSsssmTile - 1) / kSsssmTile;
+    hipLaunchKernelGGL(k_ssssm, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level, d.rseg,
+                       d.stgt, d.maps);
     return hipGetLastError();
 }
 

@@ -20,9 +20,9 @@ struct DevPlan {
     const int32_t *R_idx;
     const ChunkDev *chunks;
     const int32_t *chunk_rows;
-    const TaskDev *tasks;
-    const int32_t *maps;
-    const TileDev *tiles;
+    const int32_t *rseg;        // segment of every row of R_idx
+    const int64_t *stgt;        // SSSSM target base per segment pair
+    const int32_t *maps;        // SSSSM row / column offset tables
     const int64_t *slot;
     const int64_t *a_rowptr;
     const int32_t *a_colidx;
@@ -48,7 +48,7 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s);
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s);
-hipError_t launch_ssssm(const DevPlan &d, int level, int64_t ntiles, hipStream_t s);
+hipError_t launch_ssssm(const DevPlan &d, int level, int m, hipStream_t s);
 
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).
 hipError_t launch_gather_perm(const DevPlan &d, const double *B, int64_t ld, int nc, hipStream_t s);

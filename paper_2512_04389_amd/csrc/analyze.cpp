@@ -409,7 +409,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 best.swap(ch);
                 best_rows.swap(rows_all);
                 // two coupled-row buffers (ints) precede the chunk's panel
-                ml += ((2 * mnr + 1) / 2) * 8 + 2 * 16 * 17 * 8;   // + the two 16 x 16 inverses
+                ml += ((2 * mnr + 1) / 2) * 8 + 16 * 8;   // + the pivot reciprocals
                 maxl = ml;
                 best_mnr = mnr;
                 sflops = fl;
@@ -426,6 +426,58 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             L.pad = (int32_t)best_mnr;
         }
         L.chunk_end = (int32_t)an.chunks.size();
+    }
+
+    // triangular-solve chunks and items
+    for (int64_t i = 0; i < p; ++i) {
+        LevelDev &L = an.levels[i];
+        const int32_t b = L.b;
+        L.sch_begin = (int32_t)an.schunks.size();
+        L.sitem = (int64_t)an.sitems.size() / 2;
+        int32_t item = 0;
+        auto add_chunk = [&](int32_t c0, int32_t w, int32_t nr, int64_t roff) {
+            an.schunks.push_back(ChunkDev{c0, w, nr, item, roff});
+            for (int32_t t = 0; t < w + nr; ++t) {
+                an.sitems.push_back(t < w ? c0 + t : an.chunk_rows[roff + t - w]);
+                an.sitems.push_back((c0 << 5) | w);
+            }
+            item += w + nr;
+            an.max_solve_items = std::max(an.max_solve_items, w + nr);
+        };
+        if (b <= kLdsDenseMax) {
+            for (int32_t c0 = 0; c0 < b; c0 += 16) {
+                const int32_t w = std::min(16, b - c0);
+                const int64_t roff = (int64_t)an.chunk_rows.size();
+                for (int32_t r = c0 + w; r < b; ++r) an.chunk_rows.push_back(r);
+                add_chunk(c0, w, b - c0 - w, roff);
+            }
+        } else {
+            for (int32_t c = L.chunk_begin; c < L.chunk_end; ++c) {
+                const ChunkDev C = an.chunks[c];
+                add_chunk(C.c0, C.w, C.nr, C.roff);
+            }
+        }
+        L.sch_end = (int32_t)an.schunks.size();
+        if (b >= (1 << 26) || an.max_solve_items > kSolveItems) return SLU_ERR_LIMIT;
+        // batches of consecutive chunks
+        L.sb_begin = (int32_t)an.sbatch.size() / 2;
+        int32_t items = 0, nch = 0;
+        for (int32_t c = L.sch_begin; c < L.sch_end; ++c) {
+            const ChunkDev &C = an.schunks[c];
+            const int32_t t = C.w + C.nr;
+            if (c == L.sch_begin || items + t > kSolveItems || nch == kSolveBatchChunks) {
+                an.sbatch.push_back(c);
+                an.sbatch.push_back(C.pad);
+                items = 0;
+                nch = 0;
+            }
+            items += t;
+            ++nch;
+        }
+        an.sbatch.push_back(L.sch_end);
+        an.sbatch.push_back(item);
+        L.sb_end = (int32_t)an.sbatch.size() / 2;
+        if (L.sb_end - L.sb_begin - 1 > kSolveMaxBatches) return SLU_ERR_LIMIT;
     }
 
     // compact coupled triangles for the panel solves: sizes and the
@@ -568,6 +620,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 w.max_nt = std::max(w.max_nt, L.kp / 16);
                 w.max_kp = std::max(w.max_kp, L.kp);
                 w.max_m = std::max(w.max_m, L.m);
+                w.max_b = std::max(w.max_b, L.b);
                 if (L.b <= kLdsDenseMax) w.any_dense = 1; else w.any_chunked = 1;
             }
             w.end = (int32_t)an.wave_levels.size();

@@ -43,6 +43,9 @@ struct LevelDev {
     int32_t kp;                 // kappa rounded up to a multiple of 16
     int32_t trow;               // offset into trow_ptr
     int32_t pad;                // chunked GETRF: largest coupled-row count of a chunk
+    int32_t sch_begin, sch_end; // triangular-solve chunks in schunks
+    int32_t sb_begin, sb_end;   // solve batch records (sbatch pairs), end = sentinel
+    int64_t sitem;              // first solve item of the level in sitems
 };
 
 // One column chunk of the right-looking GETRF of D_i: local columns
@@ -62,6 +65,7 @@ struct WaveInfo {
     int32_t max_m;              // largest panel row count
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
+    int32_t max_b;              // largest diagonal block
 };
 
 struct Segment {
@@ -87,6 +91,20 @@ struct Analysis {
     std::vector<Segment> segs;
     std::vector<ChunkDev> chunks;
     std::vector<int32_t> chunk_rows; // local rows
+    // Triangular solves inside D_i walk column chunks of at most 16 columns
+    // (the GETRF chunks of a chunked block; 16-column chunks coupled to all
+    // later rows of a dense block).  ChunkDev.pad holds the chunk's first item
+    // within its level; rows come from chunk_rows.  Item t of a chunk is its
+    // panel row t (t < w: chunk row c0 + t, else coupled row t - w), stored
+    // as (block-local row, c0 << 5 | w) in sitems.
+    std::vector<ChunkDev> schunks;
+    std::vector<int32_t> sitems;
+    int32_t max_solve_items = 0;     // largest w + nr of a solve chunk
+    // Solve chunks are staged through LDS in batches of consecutive chunks
+    // holding at most kSolveItems items and kSolveBatchChunks chunks; per
+    // level, sbatch holds (first chunk, first item) pairs of its batches and
+    // a closing (sch_end, item count) pair.
+    std::vector<int32_t> sbatch;
     std::vector<int32_t> R_seg;      // segment (local index) of every row of R_idx
     std::vector<int64_t> stgt;       // SSSSM target base offset per segment pair
     std::vector<int32_t> maps;       // SSSSM row / column offset tables
@@ -109,6 +127,10 @@ struct Analysis {
 
 // Tile edge of the SSSSM output tiles (one workgroup each).
 constexpr int kSsssmTile = 64;
+// LDS staging of the triangular solves: items (panel rows) and chunks per batch.
+constexpr int kSolveItems = 512;
+constexpr int kSolveBatchChunks = 64;
+constexpr int kSolveMaxBatches = 256;
 // Largest diagonal block factored in one LDS-resident chunk.
 constexpr int kLdsDenseMax = 128;
 // LDS budget of the chunked GETRF (bytes).

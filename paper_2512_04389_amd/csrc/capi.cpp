@@ -16,7 +16,7 @@ struct slu_handle {
     void *ws = nullptr;
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
-    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
+    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
         o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_norms;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
@@ -53,6 +53,9 @@ void plan_workspace(slu_handle *h) {
     h->o_R = take(an.R_idx.size() * 4);
     h->o_chunks = take(an.chunks.size() * sizeof(slu::ChunkDev));
     h->o_crows = take(an.chunk_rows.size() * 4);
+    h->o_schunks = take(an.schunks.size() * sizeof(slu::ChunkDev));
+    h->o_sitems = take(an.sitems.size() * 4);
+    h->o_sbatch = take(an.sbatch.size() * 4);
     h->o_rseg = take(an.R_seg.size() * 4);
     h->o_stgt = take(an.stgt.size() * 8);
     h->o_maps = take(an.maps.size() * 4);
@@ -100,20 +103,37 @@ int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t 
     const slu::Analysis &an = h->an;
     if (ld < an.n || ld < 1) return SLU_ERR_ARG;
     const slu::DevPlan &d = h->dev;
-    const int p = (int)an.p;
     for (int64_t c0 = 0; c0 < nrhs; c0 += h->solve_cols) {
         const int nc = (int)std::min<int64_t>(h->solve_cols, nrhs - c0);
         hipError_t e = slu::launch_gather_perm(d, B + c0 * ld, ld, nc, s);
         if (e != hipSuccess) return SLU_ERR_HIP;
-        for (int i = 0; i < p; ++i) {
-            const slu::LevelDev &L = an.levels[i];
-            if (slu::launch_fwd_diag(d, i, L.b, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
-            if (slu::launch_fwd_update(d, i, L.m, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+        // forward sweep wave by wave: the diagonal solves of a wave's levels
+        // together, then each level's update of later rows (in level order,
+        // so the sums are deterministic); the backward sweep mirrors it
+        for (const slu::WaveInfo &w : an.waves) {
+            const int nlev = w.end - w.begin;
+            if (slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s) !=
+                hipSuccess)
+                return SLU_ERR_HIP;
+            for (int q = w.begin; q < w.end; ++q) {
+                const slu::LevelDev &L = an.levels[an.wave_levels[q]];
+                if (L.m > 0 && L.kappa > 0 &&
+                    slu::launch_fwd_update(d, an.wave_levels[q], L.m, nc, trans, s) != hipSuccess)
+                    return SLU_ERR_HIP;
+            }
         }
-        for (int i = p - 1; i >= 0; --i) {
-            const slu::LevelDev &L = an.levels[i];
-            if (slu::launch_bwd_update(d, i, L.kappa, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
-            if (slu::launch_bwd_diag(d, i, L.b, nc, trans, s) != hipSuccess) return SLU_ERR_HIP;
+        for (size_t wi = an.waves.size(); wi-- > 0;) {
+            const slu::WaveInfo &w = an.waves[wi];
+            for (int q = w.begin; q < w.end; ++q) {
+                const slu::LevelDev &L = an.levels[an.wave_levels[q]];
+                if (L.m > 0 && L.kappa > 0 &&
+                    slu::launch_bwd_update(d, an.wave_levels[q], L.kappa, nc, trans, s) != hipSuccess)
+                    return SLU_ERR_HIP;
+            }
+            const int nlev = w.end - w.begin;
+            if (slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s) !=
+                hipSuccess)
+                return SLU_ERR_HIP;
         }
         e = slu::launch_scatter_perm(d, X + c0 * ld, ld, nc, s);
         if (e != hipSuccess) return SLU_ERR_HIP;
@@ -155,8 +175,14 @@ int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const s
         if (rc == SLU_OK) {
             build_transpose(h);
             // the diagonal sweeps of the solve hold b x nc doubles in LDS
-            const int64_t mb = std::max<int32_t>(h->an.max_block, 1);
-            h->solve_cols = (int)std::min<int64_t>(slu::kSolveCols, (150 * 1024) / (8 * mb));
+            // next to the staged chunk panels
+            const int mb = std::max<int32_t>(h->an.max_block, 1);
+            h->solve_cols = 0;
+            for (int nc = slu::kSolveCols; nc >= 1; --nc)
+                if (slu::solve_diag_lds_bytes(mb, nc) <= 160 * 1024) {
+                    h->solve_cols = nc;
+                    break;
+                }
             for (const slu::LevelDev &L : h->an.levels)
                 if (L.lds_getrf > 160 * 1024) rc = SLU_ERR_LIMIT;
             if (h->solve_cols < 1) rc = SLU_ERR_LIMIT;
@@ -194,6 +220,9 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_R, an.R_idx, s);
     if (e == hipSuccess) e = upload(base, h->o_chunks, an.chunks, s);
     if (e == hipSuccess) e = upload(base, h->o_crows, an.chunk_rows, s);
+    if (e == hipSuccess) e = upload(base, h->o_schunks, an.schunks, s);
+    if (e == hipSuccess) e = upload(base, h->o_sitems, an.sitems, s);
+    if (e == hipSuccess) e = upload(base, h->o_sbatch, an.sbatch, s);
     if (e == hipSuccess) e = upload(base, h->o_rseg, an.R_seg, s);
     if (e == hipSuccess) e = upload(base, h->o_stgt, an.stgt, s);
     if (e == hipSuccess) e = upload(base, h->o_maps, an.maps, s);
@@ -217,6 +246,9 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.R_idx = (const int32_t *)(base + h->o_R);
     d.chunks = (const slu::ChunkDev *)(base + h->o_chunks);
     d.chunk_rows = (const int32_t *)(base + h->o_crows);
+    d.schunks = (const slu::ChunkDev *)(base + h->o_schunks);
+    d.sitems = (const int32_t *)(base + h->o_sitems);
+    d.sbatch = (const int32_t *)(base + h->o_sbatch);
     d.rseg = (const int32_t *)(base + h->o_rseg);
     d.stgt = (const int64_t *)(base + h->o_stgt);
     d.maps = (const int32_t *)(base + h->o_maps);

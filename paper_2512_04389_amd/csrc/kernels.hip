@@ -36,12 +36,16 @@ __device__ __forceinline__ double recip(double x) {
 
 // In-place no-pivot LU of the w x w (w <= 16) leading block of the LDS array
 // A (element (i, j) at A[j * lda + i]) by wave 0: lane i holds row i, the
-// pivot row is broadcast with readlane.  Records a zero / non-finite pivot.
-__device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, int col0,
+// pivot row is broadcast with readlane.  Lane j < w leaves 1 / U(j, j) in
+// rdiag[j].  The first zero / non-finite pivot is tracked with uniform
+// scalar logic in the loop and recorded in info[0] once at the end.
+__device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, int col0, double *rdiag,
                                            unsigned long long *__restrict__ info) {
     double v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? A[j * lda + lane] : 0.0;
+    int bad = 16;
+    double myrd = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         if (k < w) {
@@ -49,8 +53,9 @@ __device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, 
 #pragma unroll
             for (int j = k; j < 16; ++j) u[j] = bcast_lane(v[j], k);
             const double piv = u[k];
-            if (lane == 0 && !(piv != 0.0 && isfinite(piv))) atomicMin(info, (unsigned long long)(col0 + k));
+            if (!(piv != 0.0 && isfinite(piv))) bad = min(bad, k);
             const double rp = recip(piv);
+            myrd = (lane == k) ? rp : myrd;
             if (lane > k) {
                 const double l = v[k] * rp;
                 v[k] = l;
@@ -63,49 +68,11 @@ __device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, 
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             if (j < w) A[j * lda + lane] = v[j];
+        rdiag[lane] = myrd;
     }
+    if (bad < 16 && lane == 0) atomicMin(info, (unsigned long long)(col0 + bad));
 }
 
-// Inverses of the factors of a w x w LU held in LDS (as left by lu16_wave0).
-// Lane j < 16 of the calling wave forms column j of U^{-1} (upper == true)
-// or of L^{-1} (unit lower); the two are meant to run in different waves.
-// Ui / Li are 16 x 16 with row stride 17, element (r, c) at [r * 17 + c];
-// rows / columns beyond w are the identity.  Each triangle row is read from
-// LDS as one batch before its products.
-__device__ __forceinline__ void tri_inverse16(const double *A, int lda, int w, int lane, bool upper,
-                                              double *Out) {
-    if (lane >= 16) return;
-    const int j = lane;
-    double x[16];
-    if (upper) {
-        double rd[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) rd[i] = i < w ? recip(A[i * lda + i]) : 1.0;
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            double row[16];
-#pragma unroll
-            for (int t = i + 1; t < 16; ++t) row[t] = (i < w && t < w) ? A[t * lda + i] : 0.0;
-            double sacc = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int t = 15; t > i; --t) sacc -= row[t] * x[t];
-            x[i] = (i <= j) ? sacc * rd[i] : 0.0;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            double row[16];
-#pragma unroll
-            for (int t = 0; t < i; ++t) row[t] = (i < w && t < w) ? A[t * lda + i] : 0.0;
-            double sacc = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int t = 0; t < i; ++t) sacc -= row[t] * x[t];
-            x[i] = (i >= j) ? sacc : 0.0;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Out[i * 17 + j] = x[i];
-}
 // ------------------------------------------------------------------ helpers
 __global__ void k_zero(double *__restrict__ p, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -150,20 +117,19 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 // LU of the dense diagonal block by one workgroup, right-looking over column
 // chunks [c0, c0 + w) (w <= 16).  Only the block rows R that S couples to a
 // chunk are touched by it:
-//   1. wave 0 factors the w x w diagonal of the chunk in registers and forms
-//      the inverses of its two triangles;
+//   1. wave 0 factors the w x w diagonal of the chunk in registers;
 //   2. the coupled rows (L = A U_cc^{-1}) and coupled columns
-//      (U = L_cc^{-1} A) are 16 x 16 x 16 FP64 MFMA products;
+//      (U = L_cc^{-1} A) are solved by substitution, one per lane;
 //   3. the four waves update the R x R trailing entries with FP64 MFMA.
-// Pivot divisions are FP64 divisions; a zero or non-finite pivot records its
-// permuted column in info[0].
+// Pivots are inverted by a reciprocal refined with two Newton steps; a zero
+// or non-finite pivot records its permuted column in info[0].
 // One column chunk of the chunked GETRF.  W = 16 is the full-width chunk
 // (every width guard folds away); W = 0 takes the width at run time (the
 // last chunk of a block).  Loads guarded per lane read a clamped, valid
 // address and select zero, so they are issued without branches.
 template <int W>
 __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, int r0, const ChunkDev &C,
-                                                 const int *Rs, double *Ui, double *Li, double *work,
+                                                 const int *Rs, const double *Rd, double *work,
                                                  unsigned long long *__restrict__ info, int wave, int lane,
                                                  int tid) {
     const int li = lane & 15, lk = lane >> 4;
@@ -229,69 +195,64 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     // barrier waits for LDS traffic only; these loads stay in flight.)
     if (nr > 0) load_tiles(wave);
     __syncthreads();
-    if (wave == 0) lu16_wave0(Pn, T, w, lane, r0 + c0, info);
-    __syncthreads();
+    // 1. the w x w diagonal of the chunk, factored in registers by wave 0
     if (wave == 0) {
+        lu16_wave0(Pn, T, w, lane, r0 + c0, const_cast<double *>(Rd), info);
         if (lane < w) {
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 if (j < w) D[c0 + lane + (size_t)(c0 + j) * b] = Pn[j * T + lane];
         }
-    } else if (wave == 1) {
-        tri_inverse16(Pn, T, w, lane, true, Ui);
-    } else if (wave == 2) {
-        tri_inverse16(Pn, T, w, lane, false, Li);
     }
     __syncthreads();
-    // coupled rows and columns: 16 x 16 output tiles, four waves
-    for (int q = wave; q < 2 * nrt; q += 4) {
-        double4_t sacc = {0, 0, 0, 0};
-        if (q < nrt) {
-            // L rows, transposed: X^T = U^{-T} A_rows^T, output element
-            // (chunk column lk + 4r, coupled row 16q + li)
-            const int ar = 16 * q + li;
-            const bool va = ar < nr;
-            const int arc = va ? ar : nr - 1;
+    // 2. coupled rows (x U_cc = a) and coupled columns (L_cc y = a): one
+    // per lane, forward substitution over the chunk's w columns with the
+    // factor entries broadcast from LDS.  Rows take items [0, nr64),
+    // columns [nr64, nr64 + nr), so no wave mixes the two kinds.
+    const int nr64 = (nr + 63) & ~63;
+    for (int it = tid; it < nr64 + nr; it += 256) {
+        double x[16];
+        if (it < nr64) {
+            if (it < nr) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * kk + lk;
-                const double a = Ui[k * 17 + li];                            // (U^{-T})[li][k]
-                const double bl = Pn[(k < w ? k : 0) * T + w + arc];
-                const double bv = (k < w && va) ? bl : 0.0;
-                sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, sacc, 0, 0, 0);
-            }
-            if (va) {
-                const size_t row = (size_t)Rs[ar];
+                for (int j = 0; j < 16; ++j) x[j] = j < w ? Pn[j * T + w + it] : 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = lk + 4 * r;
+                for (int j = 0; j < 16; ++j) {
                     if (j < w) {
-                        Pn[j * T + w + ar] = sacc[r];
-                        D[row + (size_t)(c0 + j) * b] = sacc[r];
+                        const double xj = x[j] * Rd[j];
+                        x[j] = xj;
+#pragma unroll
+                        for (int j2 = j + 1; j2 < 16; ++j2)
+                            if (j2 < w) x[j2] -= xj * Pn[j2 * T + j];          // U(j, j2)
+                    }
+                }
+                const size_t row = (size_t)Rs[it];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j < w) {
+                        Pn[j * T + w + it] = x[j];
+                        D[row + (size_t)(c0 + j) * b] = x[j];
                     }
                 }
             }
         } else {
-            // U columns, transposed: Y^T = A_cols^T L^{-T}, output element
-            // (coupled column 16q' + lk + 4r, chunk row li)
-            const int qq = q - nrt;
-            const int sc = 16 * qq + li;
-            const bool vs = sc < nr;
-            const int scc = vs ? sc : nr - 1;
+            const int sI = it - nr64;
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * kk + lk;
-                const double al = Uc[scc * wu + (k < w ? k : 0)];
-                const double a = (k < w && vs) ? al : 0.0;                   // (A_cols^T)[li][k]
-                const double bv = Li[li * 17 + k];                            // (L^{-T})[k][li]
-                sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, sacc, 0, 0, 0);
+            for (int j = 0; j < 16; ++j) x[j] = j < w ? Uc[sI * wu + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < w) {
+#pragma unroll
+                    for (int j2 = j + 1; j2 < 16; ++j2)
+                        if (j2 < w) x[j2] -= Pn[j * T + j2] * x[j];            // L(j2, j)
+                }
             }
+            double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int s2 = 16 * qq + lk + 4 * r;
-                if (s2 < nr && li < w) {
-                    Uc[s2 * wu + li] = sacc[r];
-                    D[c0 + li + (size_t)Rs[s2] * b] = sacc[r];
+            for (int j = 0; j < 16; ++j) {
+                if (j < w) {
+                    Uc[sI * wu + j] = x[j];
+                    col[j] = x[j];
                 }
             }
         }
@@ -342,9 +303,8 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
     const int maxnr = L.pad;                    // largest coupled-row count of a chunk
     int *Rbuf0 = (int *)lds;                    // coupled rows of the current / next chunk
     int *Rbuf1 = Rbuf0 + maxnr;
-    double *Ui = lds + ((2 * maxnr + 1) >> 1);  // 16 x 17 inverse of U_cc
-    double *Li = Ui + 16 * 17;                  // 16 x 17 inverse of L_cc
-    double *work = Li + 16 * 17;
+    double *Rd = lds + ((2 * maxnr + 1) >> 1);  // 1 / U(j, j) of the current chunk
+    double *work = Rd + 16;
     {
         const ChunkDev C = chunks[L.chunk_begin];
         for (int q = tid; q < C.nr; q += 256) Rbuf0[q] = crows[C.roff + q];
@@ -361,9 +321,9 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
             for (int q = tid; q < Cn.nr; q += 256) Rn[q] = crows[Cn.roff + q];
         }
         if (C.w == 16)
-            getrf_chunk_step<16>(D, b, L.r0, C, Rs, Ui, Li, work, info, wave, lane, tid);
+            getrf_chunk_step<16>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
         else
-            getrf_chunk_step<0>(D, b, L.r0, C, Rs, Ui, Li, work, info, wave, lane, tid);
+            getrf_chunk_step<0>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
     }
 }
 
@@ -891,70 +851,207 @@ hipError_t launch_scatter_perm(const DevPlan &d, double *X, int64_t ld, int nc, 
     return hipGetLastError();
 }
 
-// Lower-triangular sweep inside D_i.  trans == 0: unit lower L (D[r + k*b],
-// r > k).  trans == 1: U^T, lower with diagonal (U^T[r][k] = D[k + r*b]).
-__global__ __launch_bounds__(1024) void k_fwd_diag(const double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                   int level, double *__restrict__ W, int64_t n, int nc, int trans) {
-    extern __shared__ double cv[];  // cv[c*b + r]
-    const LevelDev L = levels[level];
+// ------------------------------------------------- triangular solves in D_i
+// Value of lane J of each 16-lane row in every lane of that row (DPP
+// row_newbcast, two 32-bit moves).
+template <int J>
+__device__ __forceinline__ double bcast16(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x150 + J, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x150 + J, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Forward substitution with a w x w lower triangle F held by the 16 lanes of
+// a row: lane i has x_i and its row f[j] = F(i, j); diagonal scaled by dinv
+// unless the triangle has a unit diagonal.
+template <int J>
+__device__ __forceinline__ void tri_fwd16(double &xi, const double (&f)[16], double dinv, int i, int w,
+                                          bool unit) {
+    if (J < w) {
+        xi = (!unit && i == J) ? xi * dinv : xi;
+        const double xj = bcast16<J>(xi);
+        xi = (i > J) ? xi - f[J] * xj : xi;
+    }
+    if constexpr (J + 1 < 16) tri_fwd16<J + 1>(xi, f, dinv, i, w, unit);
+}
+
+// Backward substitution with a w x w upper triangle G: lane i has x_i and
+// g[j] = G(i, j).
+template <int J>
+__device__ __forceinline__ void tri_bwd16(double &xi, const double (&g)[16], double dinv, int i, int w,
+                                          bool unit) {
+    if (J < w) {
+        xi = (!unit && i == J) ? xi * dinv : xi;
+        const double xj = bcast16<J>(xi);
+        xi = (i < J) ? xi - g[J] * xj : xi;
+    }
+    if constexpr (J > 0) tri_bwd16<J - 1>(xi, g, dinv, i, w, unit);
+}
+
+// Solves with the diagonal blocks of all levels of a wave, one workgroup per
+// level, on nc right-hand sides of the permuted work block W (x of the block
+// in LDS throughout).  FWD: x_i <- F^{-1} x_i with F = L_ii (trans == 0,
+// unit) or U_ii^T (trans == 1); otherwise x_i <- G^{-1} x_i with G = U_ii
+// (trans == 0) or L_ii^T (trans == 1, unit).  The block is walked in column
+// chunks (ascending forward, descending backward):
+//   forward:  x_c <- F_cc^{-1} x_c, then x_R -= F(R, c) x_c
+//   backward: x_c -= G(c, R) x_R,   then x_c <- G_cc^{-1} x_c
+// with R the coupled rows of the chunk.  Chunk panels are staged in LDS a
+// batch of chunks at a time: item t of a chunk (panel row t, block row
+// row_t) holds the 16 entries (row_t, c0 + j) of D_i ("column panel",
+// forward L / backward L^T) or (c0 + j, row_t) ("row panel", forward U^T /
+// backward U), which covers both the chunk's triangles and its coupled
+// part.  The triangles are solved by 16 lanes per right-hand side with DPP
+// broadcasts; the coupled updates by all threads from LDS.
+constexpr int kPnLd = 17;
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ slab,
+                                                    const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl,
+                                                    const ChunkDev *__restrict__ schunks,
+                                                    const int32_t *__restrict__ sitems,
+                                                    const int32_t *__restrict__ sbatch, double *__restrict__ W,
+                                                    int64_t n, int nc, int trans) {
+    extern __shared__ double lds[];
+    const LevelDev L = levels[lvl[blockIdx.x]];
     const int b = L.b;
     const double *__restrict__ D = slab + L.offD;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < b * nc; e += nt) {
+    const int tid = threadIdx.x;
+    const bool colpanel = FWD ? trans == 0 : trans != 0;
+    const bool unit = FWD ? trans == 0 : trans != 0;
+    double *xs = lds;                                        // xs[c * b + r]
+    double *Pn = lds + (((size_t)b * nc + 1) & ~(size_t)1);  // kSolveItems x kPnLd
+    int *rowb = (int *)(Pn + kSolveItems * kPnLd);           // block row of every item
+    int *desc = rowb + kSolveItems;                          // (c0, w, nr, item) per chunk
+    int *brec = desc + 4 * kSolveBatchChunks;                // batch records of the level
+    const int nb = L.sb_end - L.sb_begin - 1;
+    for (int q = tid; q < 2 * (nb + 1); q += 256) brec[q] = sbatch[2 * (size_t)L.sb_begin + q];
+    for (int e = tid; e < b * nc; e += 256) {
         const int c = e / b, r = e - c * b;
-        cv[e] = W[L.r0 + r + (size_t)c * n];
+        xs[e] = W[L.r0 + r + (size_t)c * n];
     }
     __syncthreads();
-    for (int k = 0; k < b; ++k) {
-        if (trans) {
-            if (tid < nc) cv[tid * b + k] = cv[tid * b + k] / D[k + (size_t)k * b];
-            __syncthreads();
+    const int c16 = tid >> 4, i16 = tid & 15;    // triangle lanes: right-hand side, row
+    for (int bq = 0; bq < nb; ++bq) {
+        const int bi = FWD ? bq : nb - 1 - bq;
+        const int kb = brec[2 * bi], ke = brec[2 * bi + 2];
+        const int i0 = brec[2 * bi + 1], i1 = brec[2 * bi + 3];
+        // stage the batch: chunk descriptors and the 16 entries of every item
+        for (int q = tid; q < ke - kb; q += 256) {
+            const ChunkDev C = schunks[kb + q];
+            desc[4 * q] = C.c0;
+            desc[4 * q + 1] = C.w;
+            desc[4 * q + 2] = C.nr;
+            desc[4 * q + 3] = C.pad;
         }
-        const int rows = b - k - 1;
-        for (int e = tid; e < rows * nc; e += nt) {
-            const int c = e / rows, r = k + 1 + (e - c * rows);
-            const double lv = trans ? D[k + (size_t)r * b] : D[r + (size_t)k * b];
-            cv[c * b + r] -= lv * cv[c * b + k];
+        const int total = (i1 - i0) * 16;
+        for (int e0 = tid; e0 < total; e0 += 256 * 4) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = min(e0 + 256 * u, total - 1);
+                const int it = i0 + (e >> 4), j = e & 15;
+                const int row = sitems[2 * (L.sitem + it)];
+                const int cw = sitems[2 * (L.sitem + it) + 1];
+                const int c0 = cw >> 5, w = cw & 31;
+                // entries j >= w are never read: clamp to a valid address
+                const int col = c0 + min(j, w - 1);
+                v[u] = colpanel ? D[row + (size_t)col * b] : D[col + (size_t)row * b];
+                if (e0 + 256 * u < total && j == 0) rowb[e >> 4] = row;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < total) Pn[(e >> 4) * kPnLd + (e & 15)] = v[u];
+            }
         }
         __syncthreads();
+        for (int kq = 0; kq < ke - kb; ++kq) {
+            const int kk = FWD ? kq : ke - kb - 1 - kq;
+            const int c0 = desc[4 * kk], w = desc[4 * kk + 1], nr = desc[4 * kk + 2];
+            const int ib = desc[4 * kk + 3] - i0;
+            const double *__restrict__ base = Pn + (size_t)ib * kPnLd;
+            const int *__restrict__ rows = rowb + ib;         // rows[t], t >= w: coupled rows
+            if (!FWD) {
+                // x_c -= G(c, R) x_R: 16 lanes per (row i, right-hand side)
+                const int nic = w * nc;
+                for (int q0 = 0; q0 < nic; q0 += 16) {
+                    const int q = q0 + c16;
+                    double acc = 0.0;
+                    int c = 0, i = 0;
+                    if (q < nic) {
+                        c = q / w;
+                        i = q - c * w;
+                        for (int sI = i16; sI < nr; sI += 16)
+                            acc += base[(w + sI) * kPnLd + i] * xs[c * b + rows[w + sI]];
+                    }
+                    acc += __shfl_xor(acc, 8, 16);
+                    acc += __shfl_xor(acc, 4, 16);
+                    acc += __shfl_xor(acc, 2, 16);
+                    acc += __shfl_xor(acc, 1, 16);
+                    if (q < nic && i16 == 0) xs[c * b + c0 + i] -= acc;
+                }
+                __syncthreads();
+            }
+            if (c16 < nc) {
+                // the chunk's triangle: 16 lanes per right-hand side
+                const int i = i16;
+                const int ic = i < w ? i : w - 1;
+                double xi = xs[c16 * b + c0 + ic];
+                double f[16];
+                if (FWD) {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) f[j] = base[ic * kPnLd + j];     // F(i, j)
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) f[j] = base[min(j, w - 1) * kPnLd + ic];   // G(i, j)
+                }
+                const double dinv = unit ? 1.0 : 1.0 / base[ic * kPnLd + ic];
+                if (FWD)
+                    tri_fwd16<0>(xi, f, dinv, i, w, unit);
+                else
+                    tri_bwd16<15>(xi, f, dinv, i, w, unit);
+                if (i < w) xs[c16 * b + c0 + i] = xi;
+            }
+            __syncthreads();
+            if (FWD) {
+                // x_R -= F(R, c) x_c
+                for (int q = tid; q < nr * nc; q += 256) {
+                    const int c = q / nr, sI = q - c * nr;
+                    const double *__restrict__ prow = base + (size_t)(w + sI) * kPnLd;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+                        if (j < w) acc += prow[j] * xs[c * b + c0 + j];
+                    xs[c * b + rows[w + sI]] -= acc;
+                }
+                __syncthreads();
+            }
+        }
     }
-    for (int e = tid; e < b * nc; e += nt) {
+    for (int e = tid; e < b * nc; e += 256) {
         const int c = e / b, r = e - c * b;
-        W[L.r0 + r + (size_t)c * n] = cv[e];
+        W[L.r0 + r + (size_t)c * n] = xs[e];
     }
 }
 
-// Upper-triangular sweep inside D_i.  trans == 0: U (D[r + k*b], r <= k).
-// trans == 1: L^T, unit upper (L^T[r][k] = D[k + r*b], r < k).
-__global__ __launch_bounds__(1024) void k_bwd_diag(const double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                   int level, double *__restrict__ W, int64_t n, int nc, int trans) {
-    extern __shared__ double cv[];
-    const LevelDev L = levels[level];
-    const int b = L.b;
-    const double *__restrict__ D = slab + L.offD;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < b * nc; e += nt) {
-        const int c = e / b, r = e - c * b;
-        cv[e] = W[L.r0 + r + (size_t)c * n];
-    }
-    __syncthreads();
-    for (int k = b - 1; k >= 0; --k) {
-        if (!trans) {
-            if (tid < nc) cv[tid * b + k] = cv[tid * b + k] / D[k + (size_t)k * b];
-            __syncthreads();
-        }
-        const int rows = k;
-        for (int e = tid; e < rows * nc; e += nt) {
-            const int c = e / rows, r = e - c * rows;
-            const double uv = trans ? D[k + (size_t)r * b] : D[r + (size_t)k * b];
-            cv[c * b + r] -= uv * cv[c * b + k];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < b * nc; e += nt) {
-        const int c = e / b, r = e - c * b;
-        W[L.r0 + r + (size_t)c * n] = cv[e];
-    }
+size_t solve_diag_lds_bytes(int max_b, int nc) {
+    return ((((size_t)max_b * nc + 1) & ~(size_t)1) + (size_t)kSolveItems * kPnLd) * sizeof(double) +
+           (size_t)(kSolveItems + 4 * kSolveBatchChunks + 2 * (kSolveMaxBatches + 1)) * sizeof(int);
+}
+
+hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
+                                  int trans, hipStream_t s) {
+    const size_t lds = solve_diag_lds_bytes(max_b, nc);
+    if (fwd)
+        hipLaunchKernelGGL(k_solve_diag<true>, dim3((unsigned)nlev), dim3(256), lds, s, d.slab, d.levels, lvl,
+                           d.schunks, d.sitems, d.sbatch, d.scratch, d.n, nc, trans);
+    else
+        hipLaunchKernelGGL(k_solve_diag<false>, dim3((unsigned)nlev), dim3(256), lds, s, d.slab, d.levels, lvl,
+                           d.schunks, d.sitems, d.sbatch, d.scratch, d.n, nc, trans);
+    return hipGetLastError();
 }
 
 // W[rows_i[a]] -= X[a, :] . W[r0 + K_i]   (X = P_i, or Qt_i when transposed)
@@ -994,17 +1091,7 @@ __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ sl
     if (threadIdx.x == 0) W[L.r0 + Kidx[L.Koff + t] + (size_t)c * n] -= acc;
 }
 
-hipError_t launch_fwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd_diag, dim3(1), dim3(1024), (size_t)b * nc * sizeof(double), s, d.slab, d.levels,
-                       level, d.scratch, d.n, nc, trans);
-    return hipGetLastError();
-}
 
-hipError_t launch_bwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s) {
-    hipLaunchKernelGGL(k_bwd_diag, dim3(1), dim3(1024), (size_t)b * nc * sizeof(double), s, d.slab, d.levels,
-                       level, d.scratch, d.n, nc, trans);
-    return hipGetLastError();
-}
 
 hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s) {
     if (m <= 0) return hipSuccess;
@@ -1070,9 +1157,11 @@ hipError_t launch_residual_norms(const DevPlan &d, const double *values, const d
 
 hipError_t setup_kernel_attributes() {
     hipError_t e;
-    e = hipFuncSetAttribute((const void *)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    e = hipFuncSetAttribute((const void *)k_solve_diag<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    e = hipFuncSetAttribute((const void *)k_solve_diag<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_getrf_wave, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;

@@ -20,6 +20,9 @@ struct DevPlan {
     const int32_t *R_idx;
     const ChunkDev *chunks;
     const int32_t *chunk_rows;
+    const ChunkDev *schunks;    // triangular-solve chunks
+    const int32_t *sitems;
+    const int32_t *sbatch;
     const int32_t *rseg;        // segment of every row of R_idx
     const int64_t *stgt;        // SSSSM target base per segment pair
     const int32_t *maps;        // SSSSM row / column offset tables
@@ -53,10 +56,12 @@ hipError_t launch_ssssm(const DevPlan &d, int level, int m, hipStream_t s);
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).
 hipError_t launch_gather_perm(const DevPlan &d, const double *B, int64_t ld, int nc, hipStream_t s);
 hipError_t launch_scatter_perm(const DevPlan &d, double *X, int64_t ld, int nc, hipStream_t s);
-hipError_t launch_fwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s);
+// LDS bytes of a diagonal-solve launch over blocks of at most max_b rows.
+size_t solve_diag_lds_bytes(int max_b, int nc);
+hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
+                                  int trans, hipStream_t s);
 hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s);
 hipError_t launch_bwd_update(const DevPlan &d, int level, int kappa, int nc, int trans, hipStream_t s);
-hipError_t launch_bwd_diag(const DevPlan &d, int level, int b, int nc, int trans, hipStream_t s);
 
 // Backward-error pieces: norms[0..nc) = ||r||, [16..) = ||x||, [32..) = ||b||, [48] = ||op(A)||.
 hipError_t launch_residual_norms(const DevPlan &d, const double *values, const double *B,

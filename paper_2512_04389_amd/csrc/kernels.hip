@@ -898,12 +898,13 @@ __device__ __forceinline__ void tri_bwd16(double &xi, const double (&g)[16], dou
 //   forward:  x_c <- F_cc^{-1} x_c, then x_R -= F(R, c) x_c
 //   backward: x_c -= G(c, R) x_R,   then x_c <- G_cc^{-1} x_c
 // with R the coupled rows of the chunk.  Chunk panels are staged in LDS a
-// batch of chunks at a time: item t of a chunk (panel row t, block row
-// row_t) holds the 16 entries (row_t, c0 + j) of D_i ("column panel",
-// forward L / backward L^T) or (c0 + j, row_t) ("row panel", forward U^T /
-// backward U), which covers both the chunk's triangles and its coupled
-// part.  The triangles are solved by 16 lanes per right-hand side with DPP
-// broadcasts; the coupled updates by all threads from LDS.
+// batch of chunks at a time by all threads: item t of a chunk (panel row t,
+// block row row_t) holds the 16 entries (row_t, c0 + j) of D_i ("column
+// panel": forward L, backward L^T) or (c0 + j, row_t) ("row panel": forward
+// U^T, backward U), which covers both the chunk's triangles and its coupled
+// part.  Each wave then owns four right-hand sides and walks the batch's
+// chunks on its own (no barriers): triangles by 16 lanes per right-hand side
+// with DPP broadcasts, coupled updates by the wave's 64 lanes.
 constexpr int kPnLd = 17;
 
 template <bool FWD>
@@ -918,27 +919,40 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
     const LevelDev L = levels[lvl[blockIdx.x]];
     const int b = L.b;
     const double *__restrict__ D = slab + L.offD;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const bool colpanel = FWD ? trans == 0 : trans != 0;
     const bool unit = FWD ? trans == 0 : trans != 0;
     double *xs = lds;                                        // xs[c * b + r]
     double *Pn = lds + (((size_t)b * nc + 1) & ~(size_t)1);  // kSolveItems x kPnLd
     int *rowb = (int *)(Pn + kSolveItems * kPnLd);           // block row of every item
-    int *desc = rowb + kSolveItems;                          // (c0, w, nr, item) per chunk
+    int *icw = rowb + kSolveItems;                           // c0 << 5 | w of every item
+    int *desc = icw + kSolveItems;                           // (c0, w, nr, item) per chunk
     int *brec = desc + 4 * kSolveBatchChunks;                // batch records of the level
     const int nb = L.sb_end - L.sb_begin - 1;
     for (int q = tid; q < 2 * (nb + 1); q += 256) brec[q] = sbatch[2 * (size_t)L.sb_begin + q];
-    for (int e = tid; e < b * nc; e += 256) {
-        const int c = e / b, r = e - c * b;
-        xs[e] = W[L.r0 + r + (size_t)c * n];
+    for (int e0 = tid; e0 < b * nc; e0 += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = min(e0 + 256 * u, b * nc - 1);
+            const int c = e / b, r = e - c * b;
+            v[u] = W[L.r0 + r + (size_t)c * n];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + 256 * u < b * nc) xs[e0 + 256 * u] = v[u];
     }
-    __syncthreads();
-    const int c16 = tid >> 4, i16 = tid & 15;    // triangle lanes: right-hand side, row
+    // this wave's right-hand sides: cw0 + g for g < ncw
+    const int cw0 = 4 * wave;
+    const int ncw = max(0, min(4, nc - cw0));
+    const int g = lane >> 4, i16 = lane & 15;
     for (int bq = 0; bq < nb; ++bq) {
+        __syncthreads();
         const int bi = FWD ? bq : nb - 1 - bq;
         const int kb = brec[2 * bi], ke = brec[2 * bi + 2];
         const int i0 = brec[2 * bi + 1], i1 = brec[2 * bi + 3];
-        // stage the batch: chunk descriptors and the 16 entries of every item
+        // stage the batch: chunk descriptors and item records first, then
+        // the 16 entries of every item with all of a thread's loads in flight
         for (int q = tid; q < ke - kb; q += 256) {
             const ChunkDev C = schunks[kb + q];
             desc[4 * q] = C.c0;
@@ -946,28 +960,40 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
             desc[4 * q + 2] = C.nr;
             desc[4 * q + 3] = C.pad;
         }
-        const int total = (i1 - i0) * 16;
-        for (int e0 = tid; e0 < total; e0 += 256 * 4) {
-            double v[4];
+        const int nit = i1 - i0;
+        for (int q = tid; q < nit; q += 256) {
+            const int2 rec = reinterpret_cast<const int2 *>(sitems)[L.sitem + i0 + q];
+            rowb[q] = rec.x;
+            icw[q] = rec.y;
+        }
+        __syncthreads();
+        {
+            // column panels: entry (item, j) is e = j * 512 + item, so that
+            // consecutive lanes take consecutive items of one column; row
+            // panels: e = item * 16 + j, the 16 entries of an item contiguous
+            constexpr int PER = kSolveItems * 16 / 256;
+            static_assert(kSolveItems == 512, "column-panel staging assumes 512 items");
+            double v[PER];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + 256 * u, total - 1);
-                const int it = i0 + (e >> 4), j = e & 15;
-                const int row = sitems[2 * (L.sitem + it)];
-                const int cw = sitems[2 * (L.sitem + it) + 1];
-                const int c0 = cw >> 5, w = cw & 31;
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + 256 * u;
+                const int it = min(colpanel ? (e & 511) : (e >> 4), nit - 1);
+                const int j = colpanel ? (e >> 9) : (e & 15);
+                const int row = rowb[it], cw = icw[it];
                 // entries j >= w are never read: clamp to a valid address
-                const int col = c0 + min(j, w - 1);
+                const int col = (cw >> 5) + min(j, (cw & 31) - 1);
                 v[u] = colpanel ? D[row + (size_t)col * b] : D[col + (size_t)row * b];
-                if (e0 + 256 * u < total && j == 0) rowb[e >> 4] = row;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + 256 * u;
-                if (e < total) Pn[(e >> 4) * kPnLd + (e & 15)] = v[u];
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + 256 * u;
+                const int it = colpanel ? (e & 511) : (e >> 4);
+                const int j = colpanel ? (e >> 9) : (e & 15);
+                if (it < nit) Pn[it * kPnLd + j] = v[u];
             }
         }
         __syncthreads();
+        if (ncw == 0) continue;
         for (int kq = 0; kq < ke - kb; ++kq) {
             const int kk = FWD ? kq : ke - kb - 1 - kq;
             const int c0 = desc[4 * kk], w = desc[4 * kk + 1], nr = desc[4 * kk + 2];
@@ -975,35 +1001,29 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
             const double *__restrict__ base = Pn + (size_t)ib * kPnLd;
             const int *__restrict__ rows = rowb + ib;         // rows[t], t >= w: coupled rows
             if (!FWD) {
-                // x_c -= G(c, R) x_R: 16 lanes per (row i, right-hand side)
-                const int nic = w * nc;
-                for (int q0 = 0; q0 < nic; q0 += 16) {
-                    const int q = q0 + c16;
-                    double acc = 0.0;
-                    int c = 0, i = 0;
-                    if (q < nic) {
-                        c = q / w;
-                        i = q - c * w;
-                        for (int sI = i16; sI < nr; sI += 16)
-                            acc += base[(w + sI) * kPnLd + i] * xs[c * b + rows[w + sI]];
-                    }
-                    acc += __shfl_xor(acc, 8, 16);
-                    acc += __shfl_xor(acc, 4, 16);
-                    acc += __shfl_xor(acc, 2, 16);
-                    acc += __shfl_xor(acc, 1, 16);
-                    if (q < nic && i16 == 0) xs[c * b + c0 + i] -= acc;
+                // x_c -= G(c, R) x_R: lpi lanes per (row i, right-hand side)
+                const int lpi = ncw == 1 ? 4 : (ncw == 2 ? 2 : 1);
+                const int item = lane / lpi, sub = lane - item * lpi;
+                const int cc = item >> 4, i = item & 15;
+                double acc = 0.0;
+                if (cc < ncw && i < w) {
+                    const double *xc = xs + (size_t)(cw0 + cc) * b;
+                    for (int sI = sub; sI < nr; sI += lpi) acc += base[(w + sI) * kPnLd + i] * xc[rows[w + sI]];
                 }
-                __syncthreads();
+                if (lpi >= 2) acc += __shfl_xor(acc, 1, 64);
+                if (lpi >= 4) acc += __shfl_xor(acc, 2, 64);
+                if (cc < ncw && i < w && sub == 0) xs[(size_t)(cw0 + cc) * b + c0 + i] -= acc;
             }
-            if (c16 < nc) {
+            if (g < ncw) {
                 // the chunk's triangle: 16 lanes per right-hand side
                 const int i = i16;
                 const int ic = i < w ? i : w - 1;
-                double xi = xs[c16 * b + c0 + ic];
+                double *xc = xs + (size_t)(cw0 + g) * b;
+                double xi = xc[c0 + ic];
                 double f[16];
                 if (FWD) {
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) f[j] = base[ic * kPnLd + j];     // F(i, j)
+                    for (int j = 0; j < 16; ++j) f[j] = base[ic * kPnLd + j];               // F(i, j)
                 } else {
 #pragma unroll
                     for (int j = 0; j < 16; ++j) f[j] = base[min(j, w - 1) * kPnLd + ic];   // G(i, j)
@@ -1013,24 +1033,24 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
                     tri_fwd16<0>(xi, f, dinv, i, w, unit);
                 else
                     tri_bwd16<15>(xi, f, dinv, i, w, unit);
-                if (i < w) xs[c16 * b + c0 + i] = xi;
+                if (i < w) xc[c0 + i] = xi;
             }
-            __syncthreads();
             if (FWD) {
-                // x_R -= F(R, c) x_c
-                for (int q = tid; q < nr * nc; q += 256) {
-                    const int c = q / nr, sI = q - c * nr;
+                // x_R -= F(R, c) x_c for the wave's right-hand sides
+                for (int q = lane; q < nr * ncw; q += 64) {
+                    const int cc = q / nr, sI = q - cc * nr;
+                    double *xc = xs + (size_t)(cw0 + cc) * b;
                     const double *__restrict__ prow = base + (size_t)(w + sI) * kPnLd;
                     double acc = 0.0;
 #pragma unroll
                     for (int j = 0; j < 16; ++j)
-                        if (j < w) acc += prow[j] * xs[c * b + c0 + j];
-                    xs[c * b + rows[w + sI]] -= acc;
+                        if (j < w) acc += prow[j] * xc[c0 + j];
+                    xc[rows[w + sI]] -= acc;
                 }
-                __syncthreads();
             }
         }
     }
+    __syncthreads();
     for (int e = tid; e < b * nc; e += 256) {
         const int c = e / b, r = e - c * b;
         W[L.r0 + r + (size_t)c * n] = xs[e];
@@ -1039,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
 
 size_t solve_diag_lds_bytes(int max_b, int nc) {
     return ((((size_t)max_b * nc + 1) & ~(size_t)1) + (size_t)kSolveItems * kPnLd) * sizeof(double) +
-           (size_t)(kSolveItems + 4 * kSolveBatchChunks + 2 * (kSolveMaxBatches + 1)) * sizeof(int);
+           (size_t)(2 * kSolveItems + 4 * kSolveBatchChunks + 2 * (kSolveMaxBatches + 1)) * sizeof(int);
 }
 
 hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
@@ -1055,22 +1075,63 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
 }
 
 // W[rows_i[a]] -= X[a, :] . W[r0 + K_i]   (X = P_i, or Qt_i when transposed)
-__global__ void k_fwd_update(const double *__restrict__ slab, const LevelDev *__restrict__ levels, int level,
-                             const int32_t *__restrict__ Kidx, const int32_t *__restrict__ Ridx,
-                             double *__restrict__ W, int64_t n, int nc, int trans) {
+// A workgroup takes 64 rows (one per lane); its four waves split the inner
+// index, whose W values are staged in LDS 256 at a time; the four partial
+// sums are added in LDS in a fixed order.
+constexpr int kUpdSlice = 256;
+
+__global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ slab,
+                                                    const LevelDev *__restrict__ levels, int level,
+                                                    const int32_t *__restrict__ Kidx,
+                                                    const int32_t *__restrict__ Ridx, double *__restrict__ W,
+                                                    int64_t n, int nc, int trans) {
+    __shared__ double xk[kUpdSlice * kSolveCols];
+    __shared__ double part[4][kSolveCols][64];
     const LevelDev L = levels[level];
     const int m = L.m, kap = L.kappa;
     const double *__restrict__ X = slab + (trans ? L.offQ : L.offP);
     const int32_t *__restrict__ K = Kidx + L.Koff;
-    const int32_t *__restrict__ R = Ridx + L.Roff;
-    const int64_t total = (int64_t)m * nc;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e / m), a = (int)(e - (int64_t)c * m);
-        const double *__restrict__ Wc = W + (size_t)c * n;
-        double acc = 0.0;
-        for (int t = 0; t < kap; ++t) acc += X[a + (size_t)t * m] * Wc[L.r0 + K[t]];
-        W[R[a] + (size_t)c * n] -= acc;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int a = blockIdx.x * 64 + lane;
+    const int ac = min(a, m - 1);
+    double acc[kSolveCols];
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
+    for (int t0 = 0; t0 < kap; t0 += kUpdSlice) {
+        const int nt = min(kUpdSlice, kap - t0);
+        __syncthreads();
+        for (int e = tid; e < nt * nc; e += 256) {
+            const int t = e / nc, c = e - t * nc;
+            xk[e] = W[L.r0 + K[t0 + t] + (size_t)c * n];
+        }
+        __syncthreads();
+        // this wave's inner indices t = wave + 4 u, eight loads in flight
+        for (int u0 = wave; u0 < nt; u0 += 32) {
+            double pv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pv[q] = X[ac + (size_t)(t0 + min(u0 + 4 * q, nt - 1)) * m];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int t = u0 + 4 * q;
+                if (t < nt) {
+#pragma unroll
+                    for (int c = 0; c < kSolveCols; ++c)
+                        if (c < nc) acc[c] += pv[q] * xk[t * nc + c];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c)
+        if (c < nc) part[wave][c][lane] = acc[c];
+    __syncthreads();
+    for (int e = tid; e < 64 * nc; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        const int row = blockIdx.x * 64 + r;
+        if (row < m) {
+            const double v = (part[0][c][r] + part[1][c][r]) + (part[2][c][r] + part[3][c][r]);
+            W[Ridx[L.Roff + row] + (size_t)c * n] -= v;
+        }
     }
 }
 
@@ -1095,7 +1156,7 @@ __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ sl
 
 hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    int64_t blocks = ((int64_t)m * nc + 255) / 256;
+    const int64_t blocks = ((int64_t)m + 63) / 64;
     hipLaunchKernelGGL(k_fwd_update, dim3((unsigned)blocks), dim3(256), 0, s, d.slab, d.levels, level, d.K_idx,
                        d.R_idx, d.scratch, d.n, nc, trans);
     return hipGetLastError();

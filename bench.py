@@ -60,6 +60,99 @@ def time_factor(h, vals, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+KERNEL_SOURCES = ("paper_2512_04389_amd/csrc/kernels.hip", "paper_2512_04389_amd/csrc/kernels.hpp",
+                  "paper_2512_04389_amd/csrc/analyze.cpp", "paper_2512_04389_amd/csrc/analyze.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_getrf_wave_lap3d48.json")
+KERNEL_SYMBOL = {"getrf": ("k_getrf_wave",), "panel": ("k_tri_gather", "k_panel_solve"), "ssssm": ("k_ssssm",)}
+COPY_BYTES = 256 << 20
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or kernel not in t.get("per_launch_bytes", {}):
+        return None
+    return t["per_launch_bytes"][kernel]
+
+
+def pmc_program(W):
+    """Program run under rocprofv3 --pmc: a plain copy of COPY_BYTES (the
+    calibration of the byte counters), then one factorization."""
+    import torch
+
+    import paper_2512_04389_amd as slu
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    h = slu.SparseLU(W["n"], W["rp"], W["ci"], ordering="grid_nd", grid_dims=W["dims"]).bind()
+    vals = torch.from_numpy(W["v"]).cuda()
+    h.factor(vals)
+    torch.cuda.synchronize()
+    print("[bench] pmc program done", file=sys.stderr, flush=True)
+
+
+def pmc_summarize(fetch_csv, write_csv, out):
+    """Per-launch HBM bytes of the factor kernels from two counter runs
+    (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled so that the
+    calibration copy reads / writes exactly COPY_BYTES."""
+    import csv
+
+    def load(path, counter):
+        rows = list(csv.DictReader(open(path)))
+        per = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            per.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), 0.0)
+            per[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
+        return per
+
+    fetch = load(fetch_csv, "FETCH_SIZE")
+    write = load(write_csv, "WRITE_SIZE")
+
+    def copy_kib(per):
+        vals = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        return max(vals) if vals else None
+
+    fc, wc = copy_kib(fetch), copy_kib(write)
+    fscale = COPY_BYTES / (fc * 1024.0) if fc else None
+    wscale = COPY_BYTES / (wc * 1024.0) if wc else None
+    res = {"kernel_hash": kernel_hash(), "copy_bytes": COPY_BYTES, "copy_fetch_kib": fc, "copy_write_kib": wc,
+           "fetch_scale": fscale, "write_scale": wscale, "per_launch_bytes": {}, "launches": {},
+           "fetch_bytes_total": {}, "write_bytes_total": {}}
+    for name, sym in KERNEL_SYMBOL.items():
+        fv = [v for (k, _), v in fetch.items() if any(x in k for x in sym)]
+        wv = [v for (k, _), v in write.items() if any(x in k for x in sym)]
+        if not fv or not wv or fscale is None or wscale is None:
+            continue
+        fb = sum(fv) * 1024.0 * fscale
+        wb = sum(wv) * 1024.0 * wscale
+        res["fetch_bytes_total"][name] = fb
+        res["write_bytes_total"][name] = wb
+        res["launches"][name] = len(fv)
+        res["per_launch_bytes"][name] = (fb + wb) / len(fv)
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(res))
+
+
 def cpu_baseline(W, budget_flops):
     """The oracle's right-looking LU on the first kmax pivots of the same
     matrix (a partial factorization), single thread."""
@@ -100,7 +193,13 @@ def main():
     ap.add_argument("--regular", type=int, default=500, help="regular block size to compare (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=1.5e10, help="oracle flops timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-program", action="store_true", help="calibration copy + one factor (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-launch HBM traffic summary from two counter runs")
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], TRAFFIC_FILE)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
@@ -114,6 +213,9 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device"
     W = workload(args.workload)
+    if args.pmc_program:
+        pmc_program(W)
+        return
     n = W["n"]
     print("[bench] workload %s" % W["name"], file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -127,6 +229,18 @@ def main():
     ms, wall_ms = time_factor(h, vals, args.steps, args.warmup, torch)
     F = info["flops"]
     gflops = F / (ms * 1e-3) / 1e9
+    # each factor timed on its own as well: median and minimum
+    singles = []
+    for _ in range(max(10, args.steps)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        h.factor(vals)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        singles.append(e0.elapsed_time(e1))
+    singles.sort()
+    median_ms = singles[len(singles) // 2]
 
     # per-kernel times (HIP events around every launch, separate pass)
     h.set_profiling(True)
@@ -141,13 +255,27 @@ def main():
             ent["algorithmic_flops"] = kflops[k]
             ent["tflops"] = kflops[k] / (kms * 1e-3) / 1e12
         per_kernel[k] = ent
-    dom = max(("getrf", "panel", "ssssm"), key=lambda k: kt[k][0])
-    dms, dn = kt[dom]
-    achieved = kflops[dom] / (dms * 1e-3) / 1e12
-    roofline = {"bound": "mfma" if dom == "ssssm" else "alu", "kernel": dom,
-                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "avg_launch_us": dms * 1e3 / max(dn, 1)}
+    # algorithmic bytes of GETRF: every stored entry of the diagonal blocks
+    # read and written once (FP64)
+    bptr = h.blocking()
+    bsz = np.diff(bptr).astype(np.float64)
+    getrf_bytes = float(np.sum(bsz * bsz)) * 16.0
+    bounds = {"getrf": "alu", "panel": "mfma", "ssssm": "mfma"}
+    rooflines = {}
+    for k in ("getrf", "panel", "ssssm"):
+        kms, kn = kt[k]
+        if kms <= 0:
+            continue
+        ach = kflops[k] / (kms * 1e-3) / 1e12
+        rooflines[k] = {"bound": bounds[k], "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_FP64_TFLOPS, "avg_launch_us": kms * 1e3 / max(kn, 1), "launches": kn,
+                        "traffic": stored_traffic(k)}
+    rooflines["getrf"]["hbm_achieved_GBs"] = getrf_bytes / (kt["getrf"][0] * 1e-3) / 1e9
+    rooflines["getrf"]["hbm_frac"] = rooflines["getrf"]["hbm_achieved_GBs"] / PEAK_HBM_GBS
+    rooflines["getrf"]["algorithmic_bytes_per_launch"] = getrf_bytes / max(kt["getrf"][1], 1)
+    dom = max(rooflines, key=lambda k: kt[k][0])
+    roofline = dict(rooflines[dom])
+    roofline["kernel"] = "+".join(KERNEL_SYMBOL[dom])
 
     # solve and backward error (gate), not part of the metric
     xt = synth.random_x(n, 1, seed=W["seed"])[:, 0]
@@ -193,11 +321,12 @@ def main():
                    "n": n, "nnz_a": info["nnz_a"], "nnz_s": info["nnz_s"], "flops": F,
                    "levels": info["nblocks"], "nonempty_blocks": info["nonempty_blocks"],
                    "ssssm_tasks": info["ssssm_tasks"], "parallelism": "single GPU"},
-        "wall_ms_per_step": wall_ms,
+        "wall_ms_per_step": wall_ms, "median_ms": median_ms, "min_ms": singles[0],
         "backward_error": eta, "eta_ok": eta <= 1e-12, "forward_error": fwd_err,
         "analyze_s": analyze_s, "solve_ms": solve_ms,
         "per_kernel": per_kernel,
         "roofline": roofline,
+        "rooflines": rooflines,
         "regular": out_regular,
         "cpu_baseline": cpu,
     }

@@ -157,6 +157,17 @@ int slu_backward_error(slu_handle *h, const double *values, const double *B,
                        const double *X, int64_t nrhs, int64_t ld, int transpose,
                        double *eta, void *stream);
 
+/* Gradient of a scalar loss with respect to the values of A for x = A^{-1} b
+ * (the adjoint of the solve; no section of the paper defines it): with
+ * G = A^{-T} (dloss/dx) (from slu_solve_transpose) and the solution X,
+ * grad_values[q] = -sum_c G[i, c] X[j, c] for entry q = (i, j) of A in the
+ * CSR order given to slu_analyze, i.e. -G X^T restricted to A's pattern.
+ * G, X: device float64 column-major n x nrhs with leading dimension ld;
+ * grad_values: device float64[nnz_a], overwritten.  Needs only the analysis
+ * and a bound workspace. */
+int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t nrhs,
+                       int64_t ld, double *grad_values, void *stream);
+
 int slu_get_info(const slu_handle *h, slu_info *info);
 
 /* Kernel classes for per-kernel timing. */

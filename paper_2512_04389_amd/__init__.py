@@ -14,7 +14,7 @@ from . import _abi
 from ._abi import (SLU_BLOCK_IRREGULAR, SLU_BLOCK_REGULAR, SLU_ORDER_GRID_ND,
                    SLU_ORDER_NATURAL, SLU_ORDER_USER, SluError, ZeroPivot, check, lib)
 
-__all__ = ["SparseLU", "SluError", "ZeroPivot", "lib"]
+__all__ = ["SparseLU", "SluError", "ZeroPivot", "lib", "solve"]
 
 
 def _vp(a):
@@ -66,6 +66,7 @@ class SparseLU:
                               ctypes.byref(h)), "slu_analyze")
         self._h = h
         self._ws = None
+        self._serial = 0          # bumped by every successful factor
 
     # ---------------------------------------------------------------- info
     def info(self):
@@ -112,6 +113,7 @@ class SparseLU:
         return self
 
     def factor(self, values, stream=None):
+        self._serial += 1
         rc = lib.slu_factor(self._h, _dptr(values), _stream(stream))
         if rc == _abi.SLU_ZERO_PIVOT:
             raise ZeroPivot(self.info()["zero_pivot_col"])
@@ -137,6 +139,18 @@ class SparseLU:
 
     def solve_transpose(self, B, X=None, stream=None):
         return self._solve(lib.slu_solve_transpose, B, X, stream)
+
+    def value_gradient(self, G, X, stream=None):
+        """-G X^T restricted to A's pattern, in the CSR order of the
+        analysis (see ``slu_value_gradient``)."""
+        import torch
+        Gc = (G.reshape(-1, 1) if G.dim() == 1 else G).t().contiguous()
+        Xc = (X.reshape(-1, 1) if X.dim() == 1 else X).t().contiguous()
+        nnz = int(self._rowptr[-1])
+        out = torch.empty(nnz, dtype=torch.float64, device=Gc.device)
+        check(lib.slu_value_gradient(self._h, _dptr(Gc), _dptr(Xc), Gc.shape[0], self.n, _dptr(out),
+                                     _stream(stream)), "slu_value_gradient")
+        return out
 
     def backward_error(self, values, B, X, transpose=False, stream=None):
         vec = B.dim() == 1
@@ -178,3 +192,13 @@ class SparseLU:
             self.close()
         except Exception:
             pass
+
+
+
+def solve(lu, values, B):
+    """Differentiable x = A^{-1} B for the pattern analyzed by ``lu`` (bound
+    to a workspace): factors A with ``values`` (device float64, CSR order of
+    the analysis) and solves; gradients flow to ``values`` and ``B`` (see
+    ``paper_2512_04389_amd.autograd``)."""
+    from .autograd import SparseSolve
+    return SparseSolve.apply(values, B, lu)

@@ -40,7 +40,7 @@ EXPORTS = [
     "slu_factor", "slu_solve", "slu_solve_transpose", "slu_backward_error", "slu_get_info",
     "slu_get_perm", "slu_get_blockptr", "slu_get_blocking", "slu_get_pattern",
     "slu_get_factors", "slu_error_string", "slu_free", "slu_set_profiling",
-    "slu_get_kernel_times",
+    "slu_get_kernel_times", "slu_value_gradient",
 ]
 
 
@@ -105,6 +105,7 @@ def _load():
         "slu_free": (None, [hp]),
         "slu_set_profiling": (i32, [hp, i32]),
         "slu_get_kernel_times": (i32, [hp, p, p]),
+        "slu_value_gradient": (i32, [hp, p, p, i64, i64, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

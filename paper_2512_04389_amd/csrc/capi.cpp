@@ -370,6 +370,16 @@ int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs,
     return solve_impl(h, B, X, nrhs, ld, 1, (hipStream_t)stream);
 }
 
+int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t nrhs, int64_t ld,
+                       double *grad_values, void *stream) {
+    if (!h || nrhs < 0 || (h->an.nnz_a > 0 && !grad_values) || (nrhs > 0 && (!G || !X))) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
+    if (slu::launch_value_gradient(h->dev, G, X, nrhs, ld, grad_values, (hipStream_t)stream) != hipSuccess)
+        return SLU_ERR_HIP;
+    return SLU_OK;
+}
+
 int slu_backward_error(slu_handle *h, const double *values, const double *B, const double *X, int64_t nrhs,
                        int64_t ld, int transpose, double *eta, void *stream) {
     if (!h || !eta || nrhs < 0 || (nrhs > 0 && (!B || !X || !values))) return SLU_ERR_ARG;

@@ -1197,6 +1197,31 @@ __global__ void k_residual_norms(const int64_t *__restrict__ ptr, const int32_t 
     }
 }
 
+// grad[q] = -sum_c G[i, c] X[j, c] for CSR entry q = (i, j): one thread per row.
+__global__ void k_value_gradient(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                                 const double *__restrict__ G, const double *__restrict__ X, int64_t ld,
+                                 int64_t n, int64_t nrhs, double *__restrict__ grad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            const int64_t j = colidx[q];
+            double acc = 0.0;
+            for (int64_t c = 0; c < nrhs; ++c) acc += G[i + c * ld] * X[j + c * ld];
+            grad[q] = -acc;
+        }
+    }
+}
+
+hipError_t launch_value_gradient(const DevPlan &d, const double *G, const double *X, int64_t nrhs, int64_t ld,
+                                 double *grad, hipStream_t s) {
+    if (d.n <= 0) return hipSuccess;
+    int64_t blocks = (d.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_value_gradient, dim3((unsigned)blocks), dim3(256), 0, s, d.a_rowptr, d.a_colidx, G, X,
+                       ld, d.n, nrhs, grad);
+    return hipGetLastError();
+}
+
 __global__ void k_norms_reset(unsigned long long *norms) {
     if (threadIdx.x < 64) norms[threadIdx.x] = 0ull;
 }

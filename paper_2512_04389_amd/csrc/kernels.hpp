@@ -43,6 +43,8 @@ struct DevPlan {
 constexpr int kSolveCols = 16;
 
 hipError_t setup_kernel_attributes();
+hipError_t launch_value_gradient(const DevPlan &d, const double *G, const double *X, int64_t nrhs, int64_t ld,
+                                 double *grad, hipStream_t s);
 
 hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);

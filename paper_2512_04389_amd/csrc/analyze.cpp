@@ -435,14 +435,24 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         L.sch_begin = (int32_t)an.schunks.size();
         L.sitem = (int64_t)an.sitems.size() / 2;
         int32_t item = 0;
+        // a chunk with more than kSolveItems items is cut into parts of its
+        // coupled rows; every part repeats the chunk's w rows as its first
+        // items, and parts after the first are marked (w | kSolveCont) so
+        // that only the first solves the chunk's triangle
         auto add_chunk = [&](int32_t c0, int32_t w, int32_t nr, int64_t roff) {
-            an.schunks.push_back(ChunkDev{c0, w, nr, item, roff});
-            for (int32_t t = 0; t < w + nr; ++t) {
-                an.sitems.push_back(t < w ? c0 + t : an.chunk_rows[roff + t - w]);
-                an.sitems.push_back((c0 << 5) | w);
-            }
-            item += w + nr;
-            an.max_solve_items = std::max(an.max_solve_items, w + nr);
+            int32_t done = 0;
+            do {
+                const int32_t part = std::min(nr - done, kSolveItems - w);
+                const int32_t flag = done > 0 ? kSolveCont : 0;
+                an.schunks.push_back(ChunkDev{c0, w | flag, part, item, roff + done});
+                for (int32_t t = 0; t < w + part; ++t) {
+                    an.sitems.push_back(t < w ? c0 + t : an.chunk_rows[roff + done + t - w]);
+                    an.sitems.push_back((c0 << 5) | w);
+                }
+                item += w + part;
+                an.max_solve_items = std::max(an.max_solve_items, w + part);
+                done += part;
+            } while (done < nr);
         };
         if (b <= kLdsDenseMax) {
             for (int32_t c0 = 0; c0 < b; c0 += 16) {
@@ -464,7 +474,7 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         int32_t items = 0, nch = 0;
         for (int32_t c = L.sch_begin; c < L.sch_end; ++c) {
             const ChunkDev &C = an.schunks[c];
-            const int32_t t = C.w + C.nr;
+            const int32_t t = (C.w & ~kSolveCont) + C.nr;
             if (c == L.sch_begin || items + t > kSolveItems || nch == kSolveBatchChunks) {
                 an.sbatch.push_back(c);
                 an.sbatch.push_back(C.pad);

@@ -131,6 +131,7 @@ constexpr int kSsssmTile = 64;
 constexpr int kSolveItems = 512;
 constexpr int kSolveBatchChunks = 64;
 constexpr int kSolveMaxBatches = 256;
+constexpr int kSolveCont = 1 << 8;   // solve chunk continuing the previous one's coupled rows
 // Largest diagonal block factored in one LDS-resident chunk.
 constexpr int kLdsDenseMax = 128;
 // LDS budget of the chunked GETRF (bytes).

@@ -996,7 +996,9 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
         if (ncw == 0) continue;
         for (int kq = 0; kq < ke - kb; ++kq) {
             const int kk = FWD ? kq : ke - kb - 1 - kq;
-            const int c0 = desc[4 * kk], w = desc[4 * kk + 1], nr = desc[4 * kk + 2];
+            const int c0 = desc[4 * kk], wf = desc[4 * kk + 1], nr = desc[4 * kk + 2];
+            const int w = wf & (kSolveCont - 1);
+            const bool first = (wf & kSolveCont) == 0;    // continuation parts skip the triangle
             const int ib = desc[4 * kk + 3] - i0;
             const double *__restrict__ base = Pn + (size_t)ib * kPnLd;
             const int *__restrict__ rows = rowb + ib;         // rows[t], t >= w: coupled rows
@@ -1014,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
                 if (lpi >= 4) acc += __shfl_xor(acc, 2, 64);
                 if (cc < ncw && i < w && sub == 0) xs[(size_t)(cw0 + cc) * b + c0 + i] -= acc;
             }
-            if (g < ncw) {
+            if (first && g < ncw) {
                 // the chunk's triangle: 16 lanes per right-hand side
                 const int i = i16;
                 const int ic = i < w ? i : w - 1;

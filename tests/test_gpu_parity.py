@@ -67,6 +67,13 @@ def test_regular_blocking_chunked_getrf(b):
              blocking="regular", block_size=b)
 
 
+def test_solve_chunks_split_beyond_staging_budget():
+    # natural order on a 600 x 4 grid has bandwidth 600: the 16-column chunks
+    # of 1200-row blocks couple about 600 rows, more than one LDS batch holds
+    n, rp, ci, v = synth.grid_laplacian((600, 4, 1))
+    run_case("band-600x4-regular-1200", n, rp, ci, v, nrhs=3, blocking="regular", block_size=1200)
+
+
 def test_random_unsymmetric_natural():
     n, rp, ci, v = _dd_random(600, 0.01, seed=5)
     run_case("random-600", n, rp, ci, v, nrhs=2)

@@ -51,6 +51,7 @@ typedef struct slu_handle slu_handle;
 /* return codes */
 #define SLU_OK 0
 #define SLU_ZERO_PIVOT 1          /* zero / non-finite pivot; see slu_info   */
+#define SLU_NOT_CONVERGED 2       /* refinement stopped above its tolerance  */
 #define SLU_ERR_ARG (-1)          /* null pointer, bad option, bad size      */
 #define SLU_ERR_ROWPTR (-2)       /* rowptr[0] != 0 or not monotone          */
 #define SLU_ERR_COLIDX (-3)       /* a column index outside [0, n)           */
@@ -111,6 +112,8 @@ typedef struct {
     int64_t zero_pivot_col;       /* permuted column of a failed pivot, or -1 */
     int32_t factored;             /* 1 after a successful slu_factor         */
     int32_t max_block;            /* largest block size                      */
+    int32_t precision;            /* SLU_PRECISION_* of the next slu_factor  */
+    int32_t reserved;
 } slu_info;
 
 /* Fill *opt with the defaults: irregular blocking, 1000 / 2 / 3 / 1,
@@ -167,6 +170,30 @@ int slu_backward_error(slu_handle *h, const double *values, const double *B,
  * and a bound workspace. */
 int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t nrhs,
                        int64_t ld, double *grad_values, void *stream);
+
+/* Factorization precision.  SLU_PRECISION_FP64: every step in FP64.
+ * SLU_PRECISION_FP32: the Schur updates (Algorithm 1's SSSSM, nearly all of
+ * the flops) take their operands rounded to FP32 and accumulate in FP32 on
+ * the FP32 matrix cores; the diagonal factorizations (with their pivot
+ * divisions), the panel solves and the storage stay FP64.  The factors are
+ * then accurate to about FP32 precision; slu_solve_refined recovers an FP64
+ * backward error by iterative refinement.  Applies to later slu_factor calls. */
+#define SLU_PRECISION_FP64 0
+#define SLU_PRECISION_FP32 1
+int slu_set_precision(slu_handle *h, int precision);
+
+/* Solve A X = B with FP64 iterative refinement on the current factors:
+ * X <- solve(B); then repeatedly R = B - A X (FP64, original A), eta as in
+ * slu_backward_error, stop when every eta <= tol, when no eta fell by half
+ * (stagnation) or after maxit corrections; otherwise X += solve(R).
+ * values: device float64[nnz_a] (the A that was factored); B, X as in
+ * slu_solve (X must not alias B).  iters (host, may be NULL): corrections
+ * applied; eta (host double[nrhs], may be NULL): final backward errors.
+ * Returns SLU_OK, SLU_NOT_CONVERGED when some eta stays above tol, or an
+ * error code.  Synchronizes `stream` once per iteration. */
+int slu_solve_refined(slu_handle *h, const double *values, const double *B, double *X,
+                      int64_t nrhs, int64_t ld, double tol, int maxit, int *iters,
+                      double *eta, void *stream);
 
 int slu_get_info(const slu_handle *h, slu_info *info);
 

@@ -140,6 +140,29 @@ class SparseLU:
     def solve_transpose(self, B, X=None, stream=None):
         return self._solve(lib.slu_solve_transpose, B, X, stream)
 
+    def set_precision(self, precision):
+        """``"fp64"`` (default) or ``"fp32"`` (Schur updates in FP32 on the
+        matrix cores, see ``slu_set_precision``) for later factorizations."""
+        code = {"fp64": _abi.SLU_PRECISION_FP64, "fp32": _abi.SLU_PRECISION_FP32}[precision]
+        check(lib.slu_set_precision(self._h, code), "slu_set_precision")
+
+    def solve_refined(self, values, B, tol=1e-12, maxit=10, stream=None):
+        """FP64 iterative refinement on the current factors; returns
+        (X, corrections applied, per-column backward errors, converged)."""
+        import torch
+        vec = B.dim() == 1
+        Bc = (B.reshape(-1, 1) if vec else B).t().contiguous()
+        Xc = torch.empty_like(Bc)
+        nrhs = Bc.shape[0]
+        eta = np.empty(nrhs, dtype=np.float64)
+        it = ctypes.c_int(0)
+        rc = lib.slu_solve_refined(self._h, _dptr(values), _dptr(Bc), _dptr(Xc), nrhs, self.n, float(tol),
+                                   int(maxit), ctypes.byref(it), _vp(eta), _stream(stream))
+        if rc != _abi.SLU_NOT_CONVERGED:
+            check(rc, "slu_solve_refined")
+        out = Xc.t()
+        return (out.reshape(-1) if vec else out), it.value, eta, rc == _abi.SLU_OK
+
     def value_gradient(self, G, X, stream=None):
         """-G X^T restricted to A's pattern, in the CSR order of the
         analysis (see ``slu_value_gradient``)."""

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libslu.so")
 
 SLU_OK = 0
 SLU_ZERO_PIVOT = 1
+SLU_NOT_CONVERGED = 2
 SLU_ERR_ARG = -1
 SLU_ERR_ROWPTR = -2
 SLU_ERR_COLIDX = -3
@@ -33,6 +34,8 @@ SLU_BLOCK_IRREGULAR = 0
 SLU_BLOCK_REGULAR = 1
 SLU_SCHEDULE_WAVES = 0
 SLU_SCHEDULE_LEVELS = 1
+SLU_PRECISION_FP64 = 0
+SLU_PRECISION_FP32 = 1
 KERNELS = ("scatter", "getrf", "panel", "ssssm")
 
 EXPORTS = [
@@ -40,7 +43,7 @@ EXPORTS = [
     "slu_factor", "slu_solve", "slu_solve_transpose", "slu_backward_error", "slu_get_info",
     "slu_get_perm", "slu_get_blockptr", "slu_get_blocking", "slu_get_pattern",
     "slu_get_factors", "slu_error_string", "slu_free", "slu_set_profiling",
-    "slu_get_kernel_times", "slu_value_gradient",
+    "slu_get_kernel_times", "slu_value_gradient", "slu_set_precision", "slu_solve_refined",
 ]
 
 
@@ -77,6 +80,8 @@ class slu_info(ctypes.Structure):
         ("zero_pivot_col", ctypes.c_int64),
         ("factored", ctypes.c_int32),
         ("max_block", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -106,6 +111,9 @@ def _load():
         "slu_set_profiling": (i32, [hp, i32]),
         "slu_get_kernel_times": (i32, [hp, p, p]),
         "slu_value_gradient": (i32, [hp, p, p, i64, i64, p, p]),
+        "slu_set_precision": (i32, [hp, i32]),
+        "slu_solve_refined": (i32, [hp, p, p, p, i64, i64, ctypes.c_double, i32, ctypes.POINTER(ctypes.c_int),
+                                    p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

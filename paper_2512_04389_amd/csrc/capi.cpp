@@ -17,7 +17,7 @@ struct slu_handle {
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
     size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
-        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_norms;
+        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_ir, o_norms;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
     std::vector<int64_t> at_vidx;
@@ -30,6 +30,7 @@ struct slu_handle {
     bool factored = false;
     int64_t zero_pivot_col = -1;
     int solve_cols = slu::kSolveCols;
+    int precision = SLU_PRECISION_FP64;
 };
 
 namespace {
@@ -69,6 +70,7 @@ void plan_workspace(slu_handle *h) {
     h->o_wlev = take(an.wave_levels.size() * 4);
     h->o_info = take(64);
     h->o_scratch = take((size_t)an.n * slu::kSolveCols * 8);
+    h->o_ir = take((size_t)2 * an.n * slu::kSolveCols * 8);
     h->o_norms = take(64 * 8);
     h->ws_bytes = o;
 }
@@ -262,6 +264,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.wave_levels = (const int32_t *)(base + h->o_wlev);
     d.info = (unsigned long long *)(base + h->o_info);
     d.scratch = (double *)(base + h->o_scratch);
+    d.ir = (double *)(base + h->o_ir);
     d.norms = (unsigned long long *)(base + h->o_norms);
     d.n = an.n;
     d.nnz_a = an.nnz_a;
@@ -346,7 +349,7 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
             const int i = an.wave_levels[q];
             const slu::LevelDev &L = an.levels[i];
             if (L.kappa > 0)
-                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.m, s));
+                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.m, h->precision == SLU_PRECISION_FP32, s));
         }
     }
 #undef SLU_TIMED
@@ -378,6 +381,60 @@ int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t 
     if (slu::launch_value_gradient(h->dev, G, X, nrhs, ld, grad_values, (hipStream_t)stream) != hipSuccess)
         return SLU_ERR_HIP;
     return SLU_OK;
+}
+
+int slu_set_precision(slu_handle *h, int precision) {
+    if (!h || (precision != SLU_PRECISION_FP64 && precision != SLU_PRECISION_FP32)) return SLU_ERR_ARG;
+    h->precision = precision;
+    return SLU_OK;
+}
+
+int slu_solve_refined(slu_handle *h, const double *values, const double *B, double *X, int64_t nrhs, int64_t ld,
+                      double tol, int maxit, int *iters, double *eta, void *stream) {
+    if (!h || nrhs < 0 || maxit < 0 || (nrhs > 0 && (!values || !B || !X || B == X))) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    if (!h->factored) return SLU_ERR_NOT_FACTORED;
+    if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const slu::DevPlan &d = h->dev;
+    const int64_t n = h->an.n;
+    double *R = d.ir, *Dv = d.ir + (size_t)n * slu::kSolveCols;
+    int used = 0;
+    bool converged = true;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += slu::kSolveCols) {
+        const int nc = (int)std::min<int64_t>(slu::kSolveCols, nrhs - c0);
+        const double *Bc = B + c0 * ld;
+        double *Xc = X + c0 * ld;
+        int rc = solve_impl(h, Bc, Xc, nc, ld, 0, s);
+        if (rc != SLU_OK) return rc;
+        double prev[slu::kSolveCols], cur[slu::kSolveCols];
+        for (int c = 0; c < nc; ++c) prev[c] = 1.0 / 0.0;
+        int it = 0;
+        for (;;) {
+            rc = slu_backward_error(h, values, Bc, Xc, nc, ld, 0, cur, stream);
+            if (rc != SLU_OK) return rc;
+            bool done = true, progress = false;
+            for (int c = 0; c < nc; ++c) {
+                if (!(cur[c] <= tol)) done = false;
+                if (cur[c] <= 0.5 * prev[c]) progress = true;
+            }
+            if (done || it >= maxit || !progress) {
+                if (!done) converged = false;
+                break;
+            }
+            if (slu::launch_residual(d, values, Bc, ld, Xc, ld, R, n, nc, s) != hipSuccess) return SLU_ERR_HIP;
+            rc = solve_impl(h, R, Dv, nc, n, 0, s);
+            if (rc != SLU_OK) return rc;
+            if (slu::launch_axpy(d, Xc, ld, Dv, n, nc, s) != hipSuccess) return SLU_ERR_HIP;
+            for (int c = 0; c < nc; ++c) prev[c] = cur[c];
+            ++it;
+        }
+        used = std::max(used, it);
+        if (eta)
+            for (int c = 0; c < nc; ++c) eta[c0 + c] = cur[c];
+    }
+    if (iters) *iters = used;
+    return converged ? SLU_OK : SLU_NOT_CONVERGED;
 }
 
 int slu_backward_error(slu_handle *h, const double *values, const double *B, const double *X, int64_t nrhs,
@@ -424,6 +481,7 @@ int slu_get_info(const slu_handle *h, slu_info *info) {
     info->zero_pivot_col = h->zero_pivot_col;
     info->factored = h->factored ? 1 : 0;
     info->max_block = an.max_block;
+    info->precision = h->precision;
     return SLU_OK;
 }
 
@@ -494,6 +552,7 @@ const char *slu_error_string(int code) {
     switch (code) {
         case SLU_OK: return "success";
         case SLU_ZERO_PIVOT: return "zero or non-finite pivot";
+        case SLU_NOT_CONVERGED: return "iterative refinement stopped above its tolerance";
         case SLU_ERR_ARG: return "invalid argument";
         case SLU_ERR_ROWPTR: return "rowptr does not start at 0 or is not monotone";
         case SLU_ERR_COLIDX: return "column index out of range";

@@ -8,6 +8,8 @@
 // could reach them has a structurally zero factor.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -15,6 +17,7 @@
 namespace slu {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // Value of a lane's double in every lane (the lane index must be the same in
 // all lanes of the wave): two v_readlane into scalar registers.
@@ -692,11 +695,20 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
 constexpr int kSsKC = 16;               // inner indices per LDS slice
 constexpr int kSsLd = kSsssmTile + 4;   // LDS row stride (doubles)
 
+//
+// F32: the product is formed in FP32 (operands rounded to FP32 when staged,
+// v_mfma_f32_16x16x4f32 with FP32 accumulation, whose result element r of
+// lane l is D[4 * (l / 16) + r][l % 16], probed on gfx950); the target is
+// updated in FP64.  This is the FP32 factorization mode: the Schur updates,
+// which hold nearly all of the flops, run at the FP32 MFMA rate.
+template <bool F32>
 __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
                                                int level, const int32_t *__restrict__ rseg,
                                                const int64_t *__restrict__ stgt,
                                                const int32_t *__restrict__ maps) {
-    __shared__ double As[2][kSsKC][kSsLd], Bs[2][kSsKC][kSsLd];
+    typedef typename std::conditional<F32, float, double>::type elem;
+    typedef typename std::conditional<F32, float4_t, double4_t>::type acc4;
+    __shared__ elem As[2][kSsKC][kSsLd], Bs[2][kSsKC][kSsLd];
     const LevelDev L = levels[level];
     const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
     const int nt = (m + kSsssmTile - 1) / kSsssmTile;
@@ -721,7 +733,7 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            rowa[bi][r] = ti * kSsssmTile + wr * 32 + bi * 16 + lk + 4 * r;
+            rowa[bi][r] = ti * kSsssmTile + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
             sa[bi][r] = RS[min(rowa[bi][r], m - 1)];
         }
     int ro[2][2][4], co[2][2][4];
@@ -753,11 +765,11 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            As[buf][kq + 4 * u][lr] = ra[u];
-            Bs[buf][kq + 4 * u][lr] = rb[u];
+            As[buf][kq + 4 * u][lr] = (elem)ra[u];
+            Bs[buf][kq + 4 * u][lr] = (elem)rb[u];
         }
     };
-    double4_t c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+    acc4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
     const int nch = kp / kSsKC;
     gload(0);
     lstore(0);
@@ -768,19 +780,26 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = 4 * kk + lk;
-            const double a0 = As[buf][k][wr * 32 + li], a1 = As[buf][k][wr * 32 + 16 + li];
-            const double b0 = Bs[buf][k][wc * 32 + li], b1 = Bs[buf][k][wc * 32 + 16 + li];
-            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
-            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
-            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+            const elem a0 = As[buf][k][wr * 32 + li], a1 = As[buf][k][wr * 32 + 16 + li];
+            const elem b0 = Bs[buf][k][wc * 32 + li], b1 = Bs[buf][k][wc * 32 + 16 + li];
+            if constexpr (F32) {
+                c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c00, 0, 0, 0);
+                c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, c01, 0, 0, 0);
+                c10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, c10, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c11, 0, 0, 0);
+            } else {
+                c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
+                c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
+                c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+            }
         }
         if (c + 1 < nch) lstore(buf ^ 1);
         __syncthreads();
     }
 
     // subtract from the targets: all loads first, then the stores
-    const double4_t acc[2][2] = {{c00, c01}, {c10, c11}};
+    const acc4 acc[2][2] = {{c00, c01}, {c10, c11}};
     int64_t off[2][2][4];
     double tv[2][2][4];
 #pragma unroll
@@ -799,14 +818,18 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - acc[bi][bj][r];
+                if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - (double)acc[bi][bj][r];
 }
 
-hipError_t launch_ssssm(const DevPlan &d, int level, int m, hipStream_t s) {
+hipError_t launch_ssssm(const DevPlan &d, int level, int m, bool f32, hipStream_t s) {
     if (m <= 0) return hipSuccess;
     const int nt = (m + kSsssmTile - 1) / kSsssmTile;
-    hipLaunchKernelGGL(k_ssssm, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level, d.rseg,
-                       d.stgt, d.maps);
+    if (f32)
+        hipLaunchKernelGGL(k_ssssm<true>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level,
+                           d.rseg, d.stgt, d.maps);
+    else
+        hipLaunchKernelGGL(k_ssssm<false>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level,
+                           d.rseg, d.stgt, d.maps);
     return hipGetLastError();
 }
 
@@ -1221,6 +1244,51 @@ hipError_t launch_value_gradient(const DevPlan &d, const double *G, const double
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_value_gradient, dim3((unsigned)blocks), dim3(256), 0, s, d.a_rowptr, d.a_colidx, G, X,
                        ld, d.n, nrhs, grad);
+    return hipGetLastError();
+}
+
+// R = B - A X for nc columns (A in CSR, original order): one thread per row.
+__global__ void k_residual(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                           const double *__restrict__ vals, const double *__restrict__ B, int64_t ldb,
+                           const double *__restrict__ X, int64_t ldx, double *__restrict__ R, int64_t ldr,
+                           int64_t n, int nc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        for (int c = 0; c < nc; ++c) {
+            const double *__restrict__ xc = X + (size_t)c * ldx;
+            double r = B[i + (size_t)c * ldb];
+            for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) r -= vals[q] * xc[colidx[q]];
+            R[i + (size_t)c * ldr] = r;
+        }
+    }
+}
+
+__global__ void k_axpy(double *__restrict__ X, int64_t ldx, const double *__restrict__ Dv, int64_t ldd, int64_t n,
+                       int nc) {
+    const int64_t total = n * nc;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t c = e / n, i = e - c * n;
+        X[i + c * ldx] += Dv[i + c * ldd];
+    }
+}
+
+hipError_t launch_residual(const DevPlan &d, const double *values, const double *B, int64_t ldb, const double *X,
+                           int64_t ldx, double *R, int64_t ldr, int nc, hipStream_t s) {
+    if (d.n <= 0) return hipSuccess;
+    int64_t blocks = (d.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks), dim3(256), 0, s, d.a_rowptr, d.a_colidx, values, B, ldb,
+                       X, ldx, R, ldr, d.n, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(const DevPlan &d, double *X, int64_t ldx, const double *Dv, int64_t ldd, int nc,
+                       hipStream_t s) {
+    int64_t blocks = (d.n * nc + 255) / 256;
+    if (blocks < 1) return hipSuccess;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks), dim3(256), 0, s, X, ldx, Dv, ldd, d.n, nc);
     return hipGetLastError();
 }
 

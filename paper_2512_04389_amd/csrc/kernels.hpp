@@ -36,6 +36,7 @@ struct DevPlan {
     const int32_t *wave_levels; // levels of every wave, consecutive
     unsigned long long *info;   // [0] smallest failed pivot column (or ~0)
     double *scratch;            // n * kSolveCols doubles
+    double *ir;                 // 2 * n * kSolveCols doubles: refinement residual and correction
     unsigned long long *norms;  // 4 * kSolveCols (non-negative doubles as bits)
     int64_t n, nnz_a, slab_doubles;
 };
@@ -43,6 +44,10 @@ struct DevPlan {
 constexpr int kSolveCols = 16;
 
 hipError_t setup_kernel_attributes();
+hipError_t launch_residual(const DevPlan &d, const double *values, const double *B, int64_t ldb, const double *X,
+                           int64_t ldx, double *R, int64_t ldr, int nc, hipStream_t s);
+hipError_t launch_axpy(const DevPlan &d, double *X, int64_t ldx, const double *Dv, int64_t ldd, int nc,
+                       hipStream_t s);
 hipError_t launch_value_gradient(const DevPlan &d, const double *G, const double *X, int64_t nrhs, int64_t ld,
                                  double *grad, hipStream_t s);
 
@@ -53,7 +58,7 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s);
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s);
-hipError_t launch_ssssm(const DevPlan &d, int level, int m, hipStream_t s);
+hipError_t launch_ssssm(const DevPlan &d, int level, int m, bool f32, hipStream_t s);
 
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).
 hipError_t launch_gather_perm(const DevPlan &d, const double *B, int64_t ld, int nc, hipStream_t s);

@@ -113,6 +113,8 @@ typedef struct {
     int32_t factored;             /* 1 after a successful slu_factor         */
     int32_t max_block;            /* largest block size                      */
     int32_t precision;            /* SLU_PRECISION_* of the next slu_factor  */
+    int32_t waves;                /* launches of GETRF / panel solves        */
+    int32_t rounds;               /* launches of the Schur updates           */
     int32_t reserved;
 } slu_info;
 
@@ -128,6 +130,21 @@ void slu_default_options(slu_options *opt);
  * SLU_ERR_PERM, SLU_ERR_NOMEM, SLU_ERR_LIMIT. */
 int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx,
                 const slu_options *opt, slu_handle **out);
+
+/* Analysis of nsys independent systems factored together: system q has
+ * order n[q] and its CSR pattern rowptr[q], colidx[q] (host arrays, copied).
+ * The systems are stacked block-diagonally in the given order (rows and
+ * columns of system q follow those of systems 0..q-1); each keeps its own
+ * ordering (SLU_ORDER_GRID_ND with grid_dims[3q..3q+2], or SLU_ORDER_NATURAL)
+ * and its own blocking (Algorithm 3 on its own block pointer, or regular
+ * blocks restarting at every system).  Levels of different systems with
+ * equal dependency height share the wave launches, and the Schur updates of
+ * a wave run in rounds with disjoint targets, so one factorization covers
+ * the whole batch.  Values, right-hand sides and solutions are the
+ * systems' arrays concatenated in the same order. */
+int slu_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowptr,
+                      const int32_t *const *colidx, const int32_t *grid_dims,
+                      const slu_options *opt, slu_handle **out);
 
 /* Device bytes the handle needs (factor storage + structure + scratch). */
 int slu_workspace_size(const slu_handle *h, size_t *bytes);
@@ -170,6 +187,15 @@ int slu_backward_error(slu_handle *h, const double *values, const double *B,
  * and a bound workspace. */
 int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t nrhs,
                        int64_t ld, double *grad_values, void *stream);
+
+/* Graph mode (enable = 1): the first slu_factor afterwards captures its
+ * whole launch sequence into a HIP graph on a stream of the library's own
+ * (default priority); later calls copy the values into the workspace and
+ * replay the graph on the caller's stream, saving the host-side launches.
+ * The graph holds kernels only; it is recaptured after slu_set_precision or
+ * slu_bind_workspace.  Per-kernel timing (slu_set_profiling) uses the
+ * launch-by-launch path.  enable = 0 releases the graph. */
+int slu_set_graph(slu_handle *h, int enable);
 
 /* Factorization precision.  SLU_PRECISION_FP64: every step in FP64.
  * SLU_PRECISION_FP32: the Schur updates (Algorithm 1's SSSSM, nearly all of

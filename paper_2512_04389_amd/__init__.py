@@ -68,6 +68,46 @@ class SparseLU:
         self._ws = None
         self._serial = 0          # bumped by every successful factor
 
+    @classmethod
+    def batch(cls, systems, ordering="natural", grid_dims=None, blocking="irregular", block_size=0,
+              sample_points=1000, step=2, max_num=3, advance=1, schedule="waves"):
+        """One handle over independent systems [(n, rowptr, colidx), ...]
+        factored together (``slu_analyze_batch``); values, right-hand sides
+        and solutions are the systems' arrays concatenated in order.
+        ``grid_dims``: one (nx, ny, nz) per system for ``"grid_nd"``."""
+        self = cls.__new__(cls)
+        ns = len(systems)
+        nvec = np.array([int(s[0]) for s in systems], dtype=np.int64)
+        rps = [np.ascontiguousarray(s[1], dtype=np.int64) for s in systems]
+        cis = [np.ascontiguousarray(s[2], dtype=np.int32) for s in systems]
+        opt = _abi.slu_options()
+        lib.slu_default_options(ctypes.byref(opt))
+        opt.sample_points, opt.step, opt.max_num, opt.advance = sample_points, step, max_num, advance
+        opt.blocking = {"irregular": SLU_BLOCK_IRREGULAR, "regular": SLU_BLOCK_REGULAR}[blocking]
+        opt.regular_block = int(block_size)
+        opt.schedule = {"waves": _abi.SLU_SCHEDULE_WAVES, "levels": _abi.SLU_SCHEDULE_LEVELS}[schedule]
+        opt.ordering = {"natural": SLU_ORDER_NATURAL, "grid_nd": SLU_ORDER_GRID_ND}[ordering]
+        dims = None
+        if ordering == "grid_nd":
+            dims = np.ascontiguousarray([tuple(int(x) for x in g) + (1,) * (3 - len(g)) for g in grid_dims],
+                                        dtype=np.int32).reshape(-1)
+        rp_ptrs = (ctypes.c_void_p * ns)(*[a.ctypes.data for a in rps])
+        ci_ptrs = (ctypes.c_void_p * ns)(*[a.ctypes.data if a.size else 0 for a in cis])
+        h = ctypes.c_void_p()
+        check(lib.slu_analyze_batch(ns, _vp(nvec), ctypes.cast(rp_ptrs, ctypes.c_void_p),
+                                    ctypes.cast(ci_ptrs, ctypes.c_void_p), _vp(dims), ctypes.byref(opt),
+                                    ctypes.byref(h)), "slu_analyze_batch")
+        self.n = int(nvec.sum())
+        offs = np.concatenate([[0], np.cumsum([int(r[-1]) for r in rps])])
+        self._rowptr = np.concatenate([[0]] + [r[1:] + o for r, o in zip(rps, offs[:-1])]).astype(np.int64)
+        self._colidx = None
+        self._perm_in = None
+        self._h = h
+        self._ws = None
+        self._serial = 0
+        self.sizes = nvec
+        return self
+
     # ---------------------------------------------------------------- info
     def info(self):
         inf = _abi.slu_info()
@@ -139,6 +179,11 @@ class SparseLU:
 
     def solve_transpose(self, B, X=None, stream=None):
         return self._solve(lib.slu_solve_transpose, B, X, stream)
+
+    def set_graph(self, enable=True):
+        """Capture the factorization's launches into a HIP graph and replay
+        it in later factors (see ``slu_set_graph``)."""
+        check(lib.slu_set_graph(self._h, 1 if enable else 0), "slu_set_graph")
 
     def set_precision(self, precision):
         """``"fp64"`` (default) or ``"fp32"`` (Schur updates in FP32 on the

@@ -44,6 +44,7 @@ EXPORTS = [
     "slu_get_perm", "slu_get_blockptr", "slu_get_blocking", "slu_get_pattern",
     "slu_get_factors", "slu_error_string", "slu_free", "slu_set_profiling",
     "slu_get_kernel_times", "slu_value_gradient", "slu_set_precision", "slu_solve_refined",
+    "slu_analyze_batch", "slu_set_graph",
 ]
 
 
@@ -81,6 +82,8 @@ class slu_info(ctypes.Structure):
         ("factored", ctypes.c_int32),
         ("max_block", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("waves", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -112,6 +115,8 @@ def _load():
         "slu_get_kernel_times": (i32, [hp, p, p]),
         "slu_value_gradient": (i32, [hp, p, p, i64, i64, p, p]),
         "slu_set_precision": (i32, [hp, i32]),
+        "slu_set_graph": (i32, [hp, i32]),
+        "slu_analyze_batch": (i32, [i64, p, p, p, p, ctypes.POINTER(slu_options), ctypes.POINTER(hp)]),
         "slu_solve_refined": (i32, [hp, p, p, p, i64, i64, ctypes.c_double, i32, ctypes.POINTER(ctypes.c_int),
                                     p, p]),
     }

@@ -201,7 +201,7 @@ int32_t lower_pos(const int32_t *b, int32_t len, int32_t v) {
 }  // namespace
 
 int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &opt,
-            Analysis *out) {
+            Analysis *out, const std::vector<int64_t> *segments) {
     int rc = validate(n, rowptr, colidx);
     if (rc != SLU_OK) return rc;
     if (opt.sample_points < 1 || opt.step < 1 || opt.max_num < 0 || opt.advance < 1)
@@ -259,14 +259,31 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         for (int64_t i = 0; i < n; ++i) an.blockptr[i + 1] = an.blockptr[i] + 2 * num[i] + 1;
     }
 
-    // blocking
-    if (opt.blocking == SLU_BLOCK_IRREGULAR) {
-        irregular_blocking(an.blockptr, opt.sample_points, opt.step, opt.max_num, opt.advance, &an.bptr);
-    } else {
-        an.bptr.clear();
-        for (int64_t r = 0; r < n; r += opt.regular_block) an.bptr.push_back(r);
-        an.bptr.push_back(n);
-        if (n == 0) an.bptr.assign(1, 0);
+    // blocking (per system when the matrix stacks independent systems)
+    {
+        std::vector<int64_t> seg = {0, n};
+        if (segments) {
+            seg = *segments;
+            if (seg.size() < 2 || seg.front() != 0 || seg.back() != n) return SLU_ERR_ARG;
+            for (size_t q = 1; q < seg.size(); ++q)
+                if (seg[q] <= seg[q - 1]) return SLU_ERR_ARG;
+        }
+        an.bptr.assign(1, 0);
+        std::vector<int64_t> part, ptr;
+        for (size_t q = 0; q + 1 < seg.size(); ++q) {
+            const int64_t s0 = seg[q], s1 = seg[q + 1];
+            if (opt.blocking == SLU_BLOCK_IRREGULAR) {
+                // the system's own block pointer: S has no entry coupling systems
+                part.assign(an.blockptr.begin() + s0, an.blockptr.begin() + s1 + 1);
+                for (int64_t &x : part) x -= an.blockptr[s0];
+                irregular_blocking(part, opt.sample_points, opt.step, opt.max_num, opt.advance, &ptr);
+            } else {
+                ptr.clear();
+                for (int64_t r = 0; r < s1 - s0; r += opt.regular_block) ptr.push_back(r);
+                ptr.push_back(s1 - s0);
+            }
+            for (size_t t = 1; t < ptr.size(); ++t) an.bptr.push_back(s0 + ptr[t]);
+        }
     }
     const int64_t p = (int64_t)an.bptr.size() - 1;
     an.p = p;
@@ -635,6 +652,53 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             }
             w.end = (int32_t)an.wave_levels.size();
             an.waves.push_back(w);
+        }
+        // SSSSM rounds: levels of a wave whose sets of target blocks are
+        // disjoint (first fit, in level order); a level whose blocks meet an
+        // earlier level's goes to a later round, so every target receives its
+        // updates in a fixed order
+        std::vector<uint64_t> used(p, 0);
+        for (WaveInfo &w : an.waves) {
+            w.round_begin = (int32_t)an.rounds.size();
+            std::vector<std::vector<int32_t>> rl;
+            for (int32_t q = w.begin; q < w.end; ++q) {
+                const int32_t i = an.wave_levels[q];
+                const LevelDev &L = an.levels[i];
+                if (L.kappa == 0 || L.m == 0) continue;
+                uint64_t busy = 0;
+                for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) busy |= used[an.segs[sgi].blk];
+                // first free round among the first 64 (tracked by the block
+                // masks); past those every level opens a round of its own
+                int32_t r = 0;
+                while (r < 64 && (busy >> r & 1)) ++r;
+                if (r >= (int32_t)rl.size()) {
+                    r = (int32_t)rl.size();
+                    rl.push_back({});
+                }
+                rl[r].push_back(i);
+                if (r < 64)
+                    for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) used[an.segs[sgi].blk] |= 1ull << r;
+            }
+            for (int32_t q = w.begin; q < w.end; ++q) {
+                const LevelDev &L = an.levels[an.wave_levels[q]];
+                for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) used[an.segs[sgi].blk] = 0;
+            }
+            for (const auto &r : rl) {
+                RoundInfo ri{};
+                ri.begin = (int32_t)an.round_levels.size();
+                int64_t t = 0;
+                for (int32_t i : r) {
+                    const int64_t nt = ((int64_t)an.levels[i].m + kSsssmTile - 1) / kSsssmTile;
+                    an.round_levels.push_back(i);
+                    an.round_tiles.push_back(t);
+                    t += nt * nt;
+                }
+                ri.end = (int32_t)an.round_levels.size();
+                ri.tiles = t;
+                if (t >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
+                an.rounds.push_back(ri);
+            }
+            w.round_end = (int32_t)an.rounds.size();
         }
     }
 

@@ -58,6 +58,12 @@ struct ChunkDev {
 // Levels that run together: equal height in the block dependency tree
 // (parent of block i = the first block below it coupled to it).  Launch
 // parameters are the maxima over the wave's levels.
+// Levels of one wave whose SSSSM targets are disjoint, launched together.
+struct RoundInfo {
+    int32_t begin, end;         // range in round_levels
+    int64_t tiles;              // SSSSM workgroups of the round
+};
+
 struct WaveInfo {
     int32_t begin, end;         // range in wave_levels
     int32_t lds_getrf;          // dynamic LDS bytes of the GETRF launch
@@ -66,6 +72,7 @@ struct WaveInfo {
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
     int32_t max_b;              // largest diagonal block
+    int32_t round_begin, round_end;
 };
 
 struct Segment {
@@ -110,6 +117,9 @@ struct Analysis {
     std::vector<int32_t> maps;       // SSSSM row / column offset tables
     std::vector<WaveInfo> waves;
     std::vector<int32_t> wave_levels;
+    std::vector<RoundInfo> rounds;
+    std::vector<int32_t> round_levels;   // levels of every round, consecutive
+    std::vector<int64_t> round_tiles;    // first SSSSM workgroup of each level within its round
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
     std::vector<int32_t> trow_idx;
     int64_t tri_doubles = 0;
@@ -138,8 +148,11 @@ constexpr int kLdsDenseMax = 128;
 constexpr int kGetrfLdsBudget = 150 * 1024;
 
 // Returns SLU_OK or an SLU_ERR_* code; fills *out.
+// segments (optional): ascending row offsets 0 = s_0 < s_1 < ... < s_k = n of
+// independent systems stacked block-diagonally; the blocking is then
+// computed on every system's own range (blocks never cross a boundary).
 int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &opt,
-            Analysis *out);
+            Analysis *out, const std::vector<int64_t> *segments = nullptr);
 
 // Geometric nested dissection of an nx x ny x nz grid (new -> old).
 void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *perm);

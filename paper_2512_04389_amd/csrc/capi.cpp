@@ -17,7 +17,7 @@ struct slu_handle {
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
     size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
-        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_info, o_scratch, o_ir, o_norms;
+        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_rlev, o_rtile, o_info, o_scratch, o_ir, o_norms, o_vals;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
     std::vector<int64_t> at_vidx;
@@ -31,6 +31,11 @@ struct slu_handle {
     int64_t zero_pivot_col = -1;
     int solve_cols = slu::kSolveCols;
     int precision = SLU_PRECISION_FP64;
+    // graph mode: the factor's launch sequence captured once, replayed
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int graph_precision = -1;
 };
 
 namespace {
@@ -68,10 +73,13 @@ void plan_workspace(slu_handle *h) {
     h->o_atv = take(h->at_vidx.size() * 8);
     h->o_perm = take(an.perm.size() * 4);
     h->o_wlev = take(an.wave_levels.size() * 4);
+    h->o_rlev = take(an.round_levels.size() * 4);
+    h->o_rtile = take(an.round_tiles.size() * 8);
     h->o_info = take(64);
     h->o_scratch = take((size_t)an.n * slu::kSolveCols * 8);
     h->o_ir = take((size_t)2 * an.n * slu::kSolveCols * 8);
     h->o_norms = take(64 * 8);
+    h->o_vals = take((size_t)an.nnz_a * 8);    // staged values of a graph replay
     h->ws_bytes = o;
 }
 
@@ -160,20 +168,17 @@ void slu_default_options(slu_options *opt) {
     opt->user_perm = nullptr;
 }
 
-int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options *opt,
-                slu_handle **out) {
-    if (!out) return SLU_ERR_ARG;
-    *out = nullptr;
-    slu_options o;
-    if (opt)
-        o = *opt;
-    else
-        slu_default_options(&o);
+}  // extern "C"
+
+namespace {
+
+int analyze_into(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &o,
+                 const std::vector<int64_t> *segments, slu_handle **out) {
     slu_handle *h = new (std::nothrow) slu_handle();
     if (!h) return SLU_ERR_NOMEM;
     int rc;
     try {
-        rc = slu::analyze(n, rowptr, colidx, o, &h->an);
+        rc = slu::analyze(n, rowptr, colidx, o, &h->an, segments);
         if (rc == SLU_OK) {
             build_transpose(h);
             // the diagonal sweeps of the solve hold b x nc doubles in LDS
@@ -199,6 +204,70 @@ int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const s
     }
     *out = h;
     return SLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options *opt,
+                slu_handle **out) {
+    if (!out) return SLU_ERR_ARG;
+    *out = nullptr;
+    slu_options o;
+    if (opt)
+        o = *opt;
+    else
+        slu_default_options(&o);
+    return analyze_into(n, rowptr, colidx, o, nullptr, out);
+}
+
+int slu_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowptr, const int32_t *const *colidx,
+                      const int32_t *grid_dims, const slu_options *opt, slu_handle **out) {
+    if (!out) return SLU_ERR_ARG;
+    *out = nullptr;
+    if (nsys < 1 || !n || !rowptr || !colidx) return SLU_ERR_ARG;
+    slu_options o;
+    if (opt)
+        o = *opt;
+    else
+        slu_default_options(&o);
+    if (o.ordering != SLU_ORDER_NATURAL && o.ordering != SLU_ORDER_GRID_ND) return SLU_ERR_ARG;
+    if (o.ordering == SLU_ORDER_GRID_ND && !grid_dims) return SLU_ERR_ARG;
+    try {
+        std::vector<int64_t> seg(1, 0), rp(1, 0);
+        std::vector<int32_t> ci, perm, p1;
+        for (int64_t q = 0; q < nsys; ++q) {
+            const int64_t ns = n[q], off = seg.back();
+            if (ns < 1 || !rowptr[q] || !colidx[q] || off + ns >= ((int64_t)1 << 31) - 1) return SLU_ERR_ARG;
+            const int64_t *r = rowptr[q];
+            if (r[0] != 0) return SLU_ERR_ROWPTR;
+            for (int64_t i = 0; i < ns; ++i) {
+                if (r[i + 1] < r[i]) return SLU_ERR_ROWPTR;
+                for (int64_t e = r[i]; e < r[i + 1]; ++e) {
+                    const int32_t c = colidx[q][e];
+                    if (c < 0 || c >= ns) return SLU_ERR_COLIDX;
+                    ci.push_back((int32_t)(c + off));
+                }
+                rp.push_back((int64_t)ci.size());
+            }
+            if (o.ordering == SLU_ORDER_GRID_ND) {
+                const int32_t *g = grid_dims + 3 * q;
+                if (g[0] < 1 || g[1] < 1 || g[2] < 1 || (int64_t)g[0] * g[1] * g[2] != ns) return SLU_ERR_ARG;
+                slu::nd_grid_order(g[0], g[1], g[2], &p1);
+            } else {
+                p1.resize(ns);
+                for (int64_t i = 0; i < ns; ++i) p1[i] = (int32_t)i;
+            }
+            for (int32_t v : p1) perm.push_back((int32_t)(v + off));
+            seg.push_back(off + ns);
+        }
+        o.ordering = SLU_ORDER_USER;
+        o.user_perm = perm.data();
+        return analyze_into(seg.back(), rp.data(), ci.data(), o, &seg, out);
+    } catch (const std::bad_alloc &) {
+        return SLU_ERR_NOMEM;
+    }
 }
 
 int slu_workspace_size(const slu_handle *h, size_t *bytes) {
@@ -236,6 +305,8 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_atv, h->at_vidx, s);
     if (e == hipSuccess) e = upload(base, h->o_perm, an.perm, s);
     if (e == hipSuccess) e = upload(base, h->o_wlev, an.wave_levels, s);
+    if (e == hipSuccess) e = upload(base, h->o_rlev, an.round_levels, s);
+    if (e == hipSuccess) e = upload(base, h->o_rtile, an.round_tiles, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return SLU_ERR_HIP;
     slu::DevPlan &d = h->dev;
@@ -262,6 +333,8 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.at_vidx = (const int64_t *)(base + h->o_atv);
     d.perm = (const int32_t *)(base + h->o_perm);
     d.wave_levels = (const int32_t *)(base + h->o_wlev);
+    d.round_levels = (const int32_t *)(base + h->o_rlev);
+    d.round_tiles = (const int64_t *)(base + h->o_rtile);
     d.info = (unsigned long long *)(base + h->o_info);
     d.scratch = (double *)(base + h->o_scratch);
     d.ir = (double *)(base + h->o_ir);
@@ -269,6 +342,10 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.n = an.n;
     d.nnz_a = an.nnz_a;
     d.slab_doubles = an.slab_doubles;
+    if (h->gexec) {   // the captured graph holds the old workspace's addresses
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
     h->ws = device_ptr;
     h->bound = true;
     h->factored = false;
@@ -319,15 +396,10 @@ struct KernelTimer {
 };
 }  // namespace
 
-int slu_factor(slu_handle *h, const double *values, void *stream) {
-    if (!h || (!values && h->an.nnz_a > 0)) return SLU_ERR_ARG;
-    if (!h->bound) return SLU_ERR_STATE;
-    hipStream_t s = (hipStream_t)stream;
+// Enqueues the whole factorization on s (no host synchronization).
+static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, KernelTimer &kt) {
     const slu::Analysis &an = h->an;
     const slu::DevPlan &d = h->dev;
-    h->factored = false;
-    h->zero_pivot_col = -1;
-    KernelTimer kt{h, s};
 #define SLU_TIMED(kind, call)                                              \
     do {                                                                   \
         if (kt.begin(kind) != hipSuccess) return SLU_ERR_HIP;              \
@@ -345,14 +417,58 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, nlev, w.max_nt, s));
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
         }
-        for (int q = w.begin; q < w.end; ++q) {
-            const int i = an.wave_levels[q];
-            const slu::LevelDev &L = an.levels[i];
-            if (L.kappa > 0)
-                SLU_TIMED(SLU_KERNEL_SSSSM, slu::launch_ssssm(d, i, L.m, h->precision == SLU_PRECISION_FP32, s));
-        }
+        for (int r = w.round_begin; r < w.round_end; ++r)
+            SLU_TIMED(SLU_KERNEL_SSSSM,
+                      slu::launch_ssssm_round(d, an.rounds[r], h->precision == SLU_PRECISION_FP32, s));
     }
 #undef SLU_TIMED
+    return SLU_OK;
+}
+
+int slu_factor(slu_handle *h, const double *values, void *stream) {
+    if (!h || (!values && h->an.nnz_a > 0)) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    const slu::DevPlan &d = h->dev;
+    h->factored = false;
+    h->zero_pivot_col = -1;
+    KernelTimer kt{h, s};
+    if (h->use_graph && !h->profiling) {
+        // the graph reads the values from the workspace copy
+        double *staged = (double *)((char *)h->ws + h->o_vals);
+        if (h->an.nnz_a > 0 &&
+            hipMemcpyAsync(staged, values, (size_t)h->an.nnz_a * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return SLU_ERR_HIP;
+        if (!h->gexec || h->graph_precision != h->precision) {
+            if (h->gexec) {
+                (void)hipGraphExecDestroy(h->gexec);
+                h->gexec = nullptr;
+            }
+            if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+                return SLU_ERR_HIP;
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return SLU_ERR_HIP;
+            KernelTimer none{h, h->cap_stream};
+            const int rc = enqueue_factor(h, staged, h->cap_stream, none);
+            const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+            if (rc != SLU_OK || ec != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc != SLU_OK ? rc : SLU_ERR_HIP;
+            }
+            const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                h->gexec = nullptr;
+                return SLU_ERR_HIP;
+            }
+            h->graph_precision = h->precision;
+        }
+        if (hipGraphLaunch(h->gexec, s) != hipSuccess) return SLU_ERR_HIP;
+    } else {
+        const int rc = enqueue_factor(h, values, s, kt);
+        if (rc != SLU_OK) return rc;
+    }
     unsigned long long flag = 0;
     if (hipMemcpyAsync(&flag, d.info, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess) return SLU_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
@@ -380,6 +496,16 @@ int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t 
     if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
     if (slu::launch_value_gradient(h->dev, G, X, nrhs, ld, grad_values, (hipStream_t)stream) != hipSuccess)
         return SLU_ERR_HIP;
+    return SLU_OK;
+}
+
+int slu_set_graph(slu_handle *h, int enable) {
+    if (!h) return SLU_ERR_ARG;
+    h->use_graph = enable != 0;
+    if (!h->use_graph && h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
     return SLU_OK;
 }
 
@@ -482,6 +608,8 @@ int slu_get_info(const slu_handle *h, slu_info *info) {
     info->factored = h->factored ? 1 : 0;
     info->max_block = an.max_block;
     info->precision = h->precision;
+    info->waves = (int32_t)an.waves.size();
+    info->rounds = (int32_t)an.rounds.size();
     return SLU_OK;
 }
 
@@ -585,6 +713,8 @@ int slu_get_kernel_times(const slu_handle *h, double *ms, int64_t *launches) {
 
 void slu_free(slu_handle *h) {
     if (!h) return;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }

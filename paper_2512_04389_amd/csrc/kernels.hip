@@ -701,18 +701,28 @@ constexpr int kSsLd = kSsssmTile + 4;   // LDS row stride (doubles)
 // lane l is D[4 * (l / 16) + r][l % 16], probed on gfx950); the target is
 // updated in FP64.  This is the FP32 factorization mode: the Schur updates,
 // which hold nearly all of the flops, run at the FP32 MFMA rate.
+//
+// One launch covers a round: levels of a wave with disjoint targets; the
+// workgroup finds its level by binary search over the levels' first tiles.
 template <bool F32>
 __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                               int level, const int32_t *__restrict__ rseg,
+                                               const int32_t *__restrict__ rlev, const int64_t *__restrict__ rtile,
+                                               int nlev, const int32_t *__restrict__ rseg,
                                                const int64_t *__restrict__ stgt,
                                                const int32_t *__restrict__ maps) {
     typedef typename std::conditional<F32, float, double>::type elem;
     typedef typename std::conditional<F32, float4_t, double4_t>::type acc4;
     __shared__ elem As[2][kSsKC][kSsLd], Bs[2][kSsKC][kSsLd];
-    const LevelDev L = levels[level];
+    int lo = 0, hi = nlev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rtile[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const LevelDev L = levels[rlev[lo]];
+    const int tile = (int)((int64_t)blockIdx.x - rtile[lo]);
     const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
     const int nt = (m + kSsssmTile - 1) / kSsssmTile;
-    const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int ti = tile / nt, tj = tile - ti * nt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int wr = wave >> 1, wc = wave & 1;
@@ -821,15 +831,17 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
                 if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - (double)acc[bi][bj][r];
 }
 
-hipError_t launch_ssssm(const DevPlan &d, int level, int m, bool f32, hipStream_t s) {
-    if (m <= 0) return hipSuccess;
-    const int nt = (m + kSsssmTile - 1) / kSsssmTile;
+hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s) {
+    if (r.tiles <= 0) return hipSuccess;
+    const int nlev = r.end - r.begin;
+    const int32_t *rl = d.round_levels + r.begin;
+    const int64_t *rt = d.round_tiles + r.begin;
     if (f32)
-        hipLaunchKernelGGL(k_ssssm<true>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level,
+        hipLaunchKernelGGL(k_ssssm<true>, dim3((unsigned)r.tiles), dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev,
                            d.rseg, d.stgt, d.maps);
     else
-        hipLaunchKernelGGL(k_ssssm<false>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, d.slab, d.levels, level,
-                           d.rseg, d.stgt, d.maps);
+        hipLaunchKernelGGL(k_ssssm<false>, dim3((unsigned)r.tiles), dim3(256), 0, s, d.slab, d.levels, rl, rt,
+                           nlev, d.rseg, d.stgt, d.maps);
     return hipGetLastError();
 }
 

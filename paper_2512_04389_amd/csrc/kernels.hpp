@@ -34,6 +34,8 @@ struct DevPlan {
     const int64_t *at_vidx;     // CSC of A: index of the entry in CSR order
     const int32_t *perm;
     const int32_t *wave_levels; // levels of every wave, consecutive
+    const int32_t *round_levels;
+    const int64_t *round_tiles;
     unsigned long long *info;   // [0] smallest failed pivot column (or ~0)
     double *scratch;            // n * kSolveCols doubles
     double *ir;                 // 2 * n * kSolveCols doubles: refinement residual and correction
@@ -58,7 +60,7 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s);
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s);
-hipError_t launch_ssssm(const DevPlan &d, int level, int m, bool f32, hipStream_t s);
+hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s);
 
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).
 hipError_t launch_gather_perm(const DevPlan &d, const double *B, int64_t ld, int nc, hipStream_t s);

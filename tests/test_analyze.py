@@ -138,3 +138,36 @@ def test_device_calls_need_workspace():
     assert _abi.lib.slu_factor(h._h, ctypes.c_void_p(8), ctypes.c_void_p(0)) == _abi.SLU_ERR_STATE
     assert _abi.lib.slu_solve(h._h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, n,
                               ctypes.c_void_p(0)) == _abi.SLU_ERR_STATE
+
+
+def test_batch_analysis_embeds_every_system():
+    # stacked systems keep their own ordering, pattern and blocking
+    import paper_2512_04389_amd as slu
+    sys_ = [synth.batch_system(s) for s in (0, 3, 130, 131)]
+    h = slu.SparseLU.batch([(x[0], x[1], x[2]) for x in sys_], ordering="grid_nd", grid_dims=[x[4] for x in sys_])
+    perm = h.perm()
+    bl = h.blocking().tolist()
+    cp, ri = h.pattern()
+    off = 0
+    for n, rp, ci, _, dims in sys_:
+        one = slu.SparseLU(n, rp, ci, ordering="grid_nd", grid_dims=dims)
+        assert np.array_equal(perm[off:off + n], one.perm() + off)
+        b1 = (one.blocking() + off).tolist()
+        i0 = bl.index(off)
+        assert bl[i0:i0 + len(b1)] == b1
+        cp1, ri1 = one.pattern()
+        assert np.array_equal(cp[off:off + n + 1] - cp[off], cp1)
+        assert np.array_equal(ri[cp[off]:cp[off + n]], ri1 + off)
+        off += n
+    assert h.n == off and bl[-1] == off
+
+
+def test_batch_analysis_errors():
+    import paper_2512_04389_amd as slu
+    n, rp, ci, _ = synth.laplacian_2d(4)
+    with pytest.raises(slu.SluError):
+        slu.SparseLU.batch([(n, rp, ci)], ordering="grid_nd", grid_dims=[(5, 4, 1)])
+    bad = ci.copy()
+    bad[0] = n
+    with pytest.raises(slu.SluError):
+        slu.SparseLU.batch([(n, rp, ci), (n, rp, bad)])

@@ -184,6 +184,47 @@ def cpu_baseline(W, budget_flops):
             "seconds": dt}
 
 
+def batch_bench(args):
+    """Batch of independent systems (2D and 3D Laplacian-like grids with
+    perturbed values, n from 2k to 20k): one handle, factor launch by
+    launch and by graph replay, FP64 and FP32 + refinement."""
+    import numpy as np
+    import torch
+
+    import paper_2512_04389_amd as slu
+    import synth
+    nsys = args.batch
+    sy = [synth.batch_system(s) for s in range(nsys)]
+    t0 = time.perf_counter()
+    h = slu.SparseLU.batch([(x[0], x[1], x[2]) for x in sy], ordering="grid_nd", grid_dims=[x[4] for x in sy])
+    analyze_s = time.perf_counter() - t0
+    h.bind()
+    info = h.info()
+    vals = torch.from_numpy(np.concatenate([x[3] for x in sy])).cuda()
+    F = info["flops"]
+    ms, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    h.set_graph(True)
+    ms_g, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    xs = synth.random_x(h.n, 1, seed=0)[:, 0]
+    B = torch.from_numpy(np.concatenate([synth.csr_matvec(x[0], x[1], x[2], x[3], xs[o:o + x[0]])
+                                         for x, o in zip(sy, np.cumsum([0] + [x[0] for x in sy[:-1]]))])).cuda()
+    X = h.solve(B)
+    eta = float(h.backward_error(vals, B, X)[0])
+    h.set_precision("fp32")
+    ms32, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    Xr, its, eta_r, conv = h.solve_refined(vals, B)
+    line = {"metric": "batched factorization GFLOP/s, 1 MI355X", "value": F / (ms_g * 1e-3) / 1e9,
+            "unit": "GFLOP/s", "config": {"workload": "%d independent systems (2D 5-point / 3D 7-point, "
+                                                      "n 2k-20k, perturbed values), nested dissection" % nsys,
+                                          "n_total": h.n, "nnz_s": info["nnz_s"], "flops": F,
+                                          "levels": info["nblocks"], "waves": info["waves"],
+                                          "rounds": info["rounds"]},
+            "analyze_s": analyze_s, "ms_launches": ms, "ms_graph": ms_g, "eta": eta,
+            "fp32": {"ms_graph": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "corrections": its,
+                     "eta": float(np.max(eta_r)), "converged": bool(conv)}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +234,7 @@ def main():
     ap.add_argument("--regular", type=int, default=500, help="regular block size to compare (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=1.5e10, help="oracle flops timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=0, help="time a batch of this many systems instead")
     ap.add_argument("--pmc-program", action="store_true", help="calibration copy + one factor (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the per-launch HBM traffic summary from two counter runs")
@@ -212,6 +254,9 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "no HIP device"
+    if args.batch > 0:
+        batch_bench(args)
+        return
     W = workload(args.workload)
     if args.pmc_program:
         pmc_program(W)

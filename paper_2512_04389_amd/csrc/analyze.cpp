@@ -686,9 +686,12 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             for (const auto &r : rl) {
                 RoundInfo ri{};
                 ri.begin = (int32_t)an.round_levels.size();
+                int32_t mmax = 0;
+                for (int32_t i : r) mmax = std::max(mmax, an.levels[i].m);
+                ri.tile = mmax < kSsssmSmallM ? 32 : kSsssmTile;
                 int64_t t = 0;
                 for (int32_t i : r) {
-                    const int64_t nt = ((int64_t)an.levels[i].m + kSsssmTile - 1) / kSsssmTile;
+                    const int64_t nt = ((int64_t)an.levels[i].m + ri.tile - 1) / ri.tile;
                     an.round_levels.push_back(i);
                     an.round_tiles.push_back(t);
                     t += nt * nt;

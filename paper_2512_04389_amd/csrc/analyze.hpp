@@ -62,6 +62,7 @@ struct ChunkDev {
 struct RoundInfo {
     int32_t begin, end;         // range in round_levels
     int64_t tiles;              // SSSSM workgroups of the round
+    int32_t tile, pad;          // tile edge (64, or 32 when every level is small)
 };
 
 struct WaveInfo {
@@ -135,8 +136,10 @@ struct Analysis {
     int32_t max_gemm_k = 0;
 };
 
-// Tile edge of the SSSSM output tiles (one workgroup each).
+// Tile edge of the SSSSM output tiles (one workgroup each), and the level
+// size below which a round uses 32 x 32 tiles.
 constexpr int kSsssmTile = 64;
+constexpr int kSsssmSmallM = 1200;
 // LDS staging of the triangular solves: items (panel rows) and chunks per batch.
 constexpr int kSolveItems = 512;
 constexpr int kSolveBatchChunks = 64;

@@ -693,7 +693,6 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
 // k = l / 16; B[k][j] with j = l % 16, k = l / 16; result element r of lane l
 // is D[l / 16 + 4 * r][l % 16] (checked on gfx950 with a lane-layout probe).
 constexpr int kSsKC = 16;               // inner indices per LDS slice
-constexpr int kSsLd = kSsssmTile + 4;   // LDS row stride (doubles)
 
 //
 // F32: the product is formed in FP32 (operands rounded to FP32 when staged,
@@ -704,28 +703,40 @@ constexpr int kSsLd = kSsssmTile + 4;   // LDS row stride (doubles)
 //
 // One launch covers a round: levels of a wave with disjoint targets; the
 // workgroup finds its level by binary search over the levels' first tiles.
-template <bool F32>
-__global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+// TT = 64: 256 threads, four waves of 32 x 32; TT = 32: one wave of 32 x 32
+// (rounds of small levels, for more workgroups).  Workgroups are dealt to
+// the eight XCDs in turn, so the tile number is remapped to give each XCD a
+// contiguous run of row-major tiles: its share of P_i stays in its L2.
+template <bool F32, int TT>
+__global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
                                                const int32_t *__restrict__ rlev, const int64_t *__restrict__ rtile,
                                                int nlev, const int32_t *__restrict__ rseg,
                                                const int64_t *__restrict__ stgt,
                                                const int32_t *__restrict__ maps) {
     typedef typename std::conditional<F32, float, double>::type elem;
     typedef typename std::conditional<F32, float4_t, double4_t>::type acc4;
-    __shared__ elem As[2][kSsKC][kSsLd], Bs[2][kSsKC][kSsLd];
+    constexpr int NT = TT == 64 ? 256 : 64;
+    constexpr int LD = TT + 4;             // LDS row stride
+    __shared__ elem As[2][kSsKC][LD], Bs[2][kSsKC][LD];
+    int64_t bid = blockIdx.x;
+    {
+        const int64_t total = gridDim.x, q = total >> 3, r = total & 7;
+        const int64_t x = bid & 7, i = bid >> 3;
+        bid = x * q + (x < r ? x : r) + i;
+    }
     int lo = 0, hi = nlev - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (rtile[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+        if (rtile[mid] <= bid) lo = mid; else hi = mid - 1;
     }
     const LevelDev L = levels[rlev[lo]];
-    const int tile = (int)((int64_t)blockIdx.x - rtile[lo]);
+    const int tile = (int)(bid - rtile[lo]);
     const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
-    const int nt = (m + kSsssmTile - 1) / kSsssmTile;
+    const int nt = (m + TT - 1) / TT;
     const int ti = tile / nt, tj = tile - ti * nt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = TT == 64 ? wave >> 1 : 0, wc = TT == 64 ? wave & 1 : 0;
 
     // epilogue addressing, loaded first so that its latency overlaps the
     // products: this lane's 8 rows a and 2 columns b of the tile
@@ -736,14 +747,14 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
     int rowa[2][4], colb[2], sa[2][4], sb[2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-        colb[bj] = tj * kSsssmTile + wc * 32 + bj * 16 + li;
+        colb[bj] = tj * TT + wc * 32 + bj * 16 + li;
         sb[bj] = RS[min(colb[bj], m - 1)];
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            rowa[bi][r] = ti * kSsssmTile + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
+            rowa[bi][r] = ti * TT + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
             sa[bi][r] = RS[min(rowa[bi][r], m - 1)];
         }
     int ro[2][2][4], co[2][2][4];
@@ -760,23 +771,24 @@ __global__ __launch_bounds__(256) void k_ssssm(double *__restrict__ slab, const 
             }
 
     // operand staging: thread (row lr, inner kq) moves P / Qt entries
-    // (row, k0 + kq + 4u), u < 4; rows past m read row m - 1 (never stored)
-    const int lr = tid & 63, kq = tid >> 6;
-    const double *__restrict__ pp = slab + L.offP + min(ti * kSsssmTile + lr, m - 1) + (size_t)kq * m;
-    const double *__restrict__ qp = slab + L.offQ + min(tj * kSsssmTile + lr, m - 1) + (size_t)kq * m;
-    double ra[4], rb[4];
+    // (row, k0 + kq + KS u), u < KU; rows past m read row m - 1 (never stored)
+    constexpr int KS = NT / TT, KU = kSsKC / KS;
+    const int lr = tid % TT, kq = tid / TT;
+    const double *__restrict__ pp = slab + L.offP + min(ti * TT + lr, m - 1) + (size_t)kq * m;
+    const double *__restrict__ qp = slab + L.offQ + min(tj * TT + lr, m - 1) + (size_t)kq * m;
+    double ra[KU], rb[KU];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ra[u] = pp[(size_t)(k0 + 4 * u) * m];
-            rb[u] = qp[(size_t)(k0 + 4 * u) * m];
+        for (int u = 0; u < KU; ++u) {
+            ra[u] = pp[(size_t)(k0 + KS * u) * m];
+            rb[u] = qp[(size_t)(k0 + KS * u) * m];
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            As[buf][kq + 4 * u][lr] = (elem)ra[u];
-            Bs[buf][kq + 4 * u][lr] = (elem)rb[u];
+        for (int u = 0; u < KU; ++u) {
+            As[buf][kq + KS * u][lr] = (elem)ra[u];
+            Bs[buf][kq + KS * u][lr] = (elem)rb[u];
         }
     };
     acc4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
@@ -836,12 +848,22 @@ hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hi
     const int nlev = r.end - r.begin;
     const int32_t *rl = d.round_levels + r.begin;
     const int64_t *rt = d.round_tiles + r.begin;
-    if (f32)
-        hipLaunchKernelGGL(k_ssssm<true>, dim3((unsigned)r.tiles), dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev,
-                           d.rseg, d.stgt, d.maps);
-    else
-        hipLaunchKernelGGL(k_ssssm<false>, dim3((unsigned)r.tiles), dim3(256), 0, s, d.slab, d.levels, rl, rt,
-                           nlev, d.rseg, d.stgt, d.maps);
+    const dim3 g((unsigned)r.tiles);
+    if (r.tile == 64) {
+        if (f32)
+            hipLaunchKernelGGL((k_ssssm<true, 64>), g, dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
+                               d.stgt, d.maps);
+        else
+            hipLaunchKernelGGL((k_ssssm<false, 64>), g, dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
+                               d.stgt, d.maps);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL((k_ssssm<true, 32>), g, dim3(64), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
+                               d.stgt, d.maps);
+        else
+            hipLaunchKernelGGL((k_ssssm<false, 32>), g, dim3(64), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
+                               d.stgt, d.maps);
+    }
     return hipGetLastError();
 }
 

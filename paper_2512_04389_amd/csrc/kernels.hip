@@ -344,15 +344,14 @@ __device__ void getrf_dense(double *__restrict__ slab, const LevelDev &L, double
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int bb = b * b;
-    for (int e0 = tid; e0 < bb; e0 += 256 * 8) {
-        double v[8];
+    // copy-in: up to 32 loads per thread in flight (clamped addresses), then
+    // the LDS stores; blocks of at most 128 rows take two such rounds
+    for (int e0 = tid; e0 < bb; e0 += 256 * 32) {
+        double v[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + 256 * u;
-            v[u] = e < bb ? D[e] : 0.0;
-        }
+        for (int u = 0; u < 32; ++u) v[u] = D[min(e0 + 256 * u, bb - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 32; ++u) {
             const int e = e0 + 256 * u;
             if (e < bb) {
                 const int c = e / b;
@@ -378,16 +377,17 @@ __device__ void getrf_dense(double *__restrict__ slab, const LevelDev &L, double
                     // pivot row c0 + k (held by lane k): all shuffles issued first
                     double u[16];
 #pragma unroll
-                    for (int j = k; j < 16; ++j) u[j] = __shfl(v0[j], k, 64);
+                    for (int j = k; j < 16; ++j) u[j] = bcast_lane(v0[j], k);
                     const double piv = u[k];
                     if (lane == 0 && !(piv != 0.0 && isfinite(piv)))
                         atomicMin(info, (unsigned long long)(L.r0 + c0 + k));
-                    const double l1 = v1[k] / piv;
+                    const double rp = recip(piv);        // one reciprocal per pivot
+                    const double l1 = v1[k] * rp;
                     v1[k] = l1;
 #pragma unroll
                     for (int j = k + 1; j < 16; ++j) v1[j] -= l1 * u[j];
                     if (lane > k) {
-                        const double l0 = v0[k] / piv;
+                        const double l0 = v0[k] * rp;
                         v0[k] = l0;
 #pragma unroll
                         for (int j = k + 1; j < 16; ++j) v0[j] -= l0 * u[j];

@@ -255,6 +255,12 @@ int slu_get_pattern(const slu_handle *h, int64_t *colptr, int32_t *rowidx);
 int slu_get_factors(const slu_handle *h, double *lval, double *uval, void *stream);
 
 const char *slu_error_string(int code);
+
+/* After a call returned SLU_ERR_HIP: the hipError_t code of the HIP call
+ * that failed (the most recent such failure on the calling thread; 0 if
+ * none), and its description from the HIP runtime. */
+int slu_last_hip_error(void);
+const char *slu_hip_error_string(int hip_code);
 void slu_free(slu_handle *h);
 
 #ifdef __cplusplus

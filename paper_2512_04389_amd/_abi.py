@@ -44,7 +44,7 @@ EXPORTS = [
     "slu_get_perm", "slu_get_blockptr", "slu_get_blocking", "slu_get_pattern",
     "slu_get_factors", "slu_error_string", "slu_free", "slu_set_profiling",
     "slu_get_kernel_times", "slu_value_gradient", "slu_set_precision", "slu_solve_refined",
-    "slu_analyze_batch", "slu_set_graph",
+    "slu_analyze_batch", "slu_set_graph", "slu_last_hip_error", "slu_hip_error_string",
 ]
 
 
@@ -91,6 +91,15 @@ class slu_info(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libslu.so is not built (run paper_2512_04389_amd.build.build())")
+    # torch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes libslu.so bind to that copy; loaded the other way round the
+    # process holds two HIP (and HSA) runtimes, and the second one to start
+    # finds no device.  Tensors and streams come from torch, so its runtime
+    # is the one the library must share.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     hp = ctypes.c_void_p
@@ -116,6 +125,8 @@ def _load():
         "slu_value_gradient": (i32, [hp, p, p, i64, i64, p, p]),
         "slu_set_precision": (i32, [hp, i32]),
         "slu_set_graph": (i32, [hp, i32]),
+        "slu_last_hip_error": (i32, []),
+        "slu_hip_error_string": (ctypes.c_char_p, [i32]),
         "slu_analyze_batch": (i32, [i64, p, p, p, p, ctypes.POINTER(slu_options), ctypes.POINTER(hp)]),
         "slu_solve_refined": (i32, [hp, p, p, p, i64, i64, ctypes.c_double, i32, ctypes.POINTER(ctypes.c_int),
                                     p, p]),
@@ -133,6 +144,10 @@ lib = _load()
 class SluError(RuntimeError):
     def __init__(self, code, where):
         msg = lib.slu_error_string(code).decode()
+        self.hip_error = 0
+        if code == SLU_ERR_HIP:
+            self.hip_error = lib.slu_last_hip_error()
+            msg += " %d: %s" % (self.hip_error, lib.slu_hip_error_string(self.hip_error).decode())
         super().__init__("%s failed: %s (code %d)" % (where, msg, code))
         self.code = code
 

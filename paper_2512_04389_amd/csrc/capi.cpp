@@ -40,6 +40,15 @@ struct slu_handle {
 
 namespace {
 
+// Code of the last failed HIP call on this thread (slu_last_hip_error).
+thread_local int t_last_hip = 0;
+
+bool hip_failed(hipError_t e) {
+    if (e == hipSuccess) return false;
+    t_last_hip = (int)e;
+    return true;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 void plan_workspace(slu_handle *h) {
@@ -116,19 +125,18 @@ int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t 
     for (int64_t c0 = 0; c0 < nrhs; c0 += h->solve_cols) {
         const int nc = (int)std::min<int64_t>(h->solve_cols, nrhs - c0);
         hipError_t e = slu::launch_gather_perm(d, B + c0 * ld, ld, nc, s);
-        if (e != hipSuccess) return SLU_ERR_HIP;
+        if (hip_failed(e)) return SLU_ERR_HIP;
         // forward sweep wave by wave: the diagonal solves of a wave's levels
         // together, then each level's update of later rows (in level order,
         // so the sums are deterministic); the backward sweep mirrors it
         for (const slu::WaveInfo &w : an.waves) {
             const int nlev = w.end - w.begin;
-            if (slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s) !=
-                hipSuccess)
+            if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
                 return SLU_ERR_HIP;
             for (int q = w.begin; q < w.end; ++q) {
                 const slu::LevelDev &L = an.levels[an.wave_levels[q]];
                 if (L.m > 0 && L.kappa > 0 &&
-                    slu::launch_fwd_update(d, an.wave_levels[q], L.m, nc, trans, s) != hipSuccess)
+                    hip_failed(slu::launch_fwd_update(d, an.wave_levels[q], L.m, nc, trans, s)))
                     return SLU_ERR_HIP;
             }
         }
@@ -137,16 +145,15 @@ int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t 
             for (int q = w.begin; q < w.end; ++q) {
                 const slu::LevelDev &L = an.levels[an.wave_levels[q]];
                 if (L.m > 0 && L.kappa > 0 &&
-                    slu::launch_bwd_update(d, an.wave_levels[q], L.kappa, nc, trans, s) != hipSuccess)
+                    hip_failed(slu::launch_bwd_update(d, an.wave_levels[q], L.kappa, nc, trans, s)))
                     return SLU_ERR_HIP;
             }
             const int nlev = w.end - w.begin;
-            if (slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s) !=
-                hipSuccess)
+            if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
                 return SLU_ERR_HIP;
         }
         e = slu::launch_scatter_perm(d, X + c0 * ld, ld, nc, s);
-        if (e != hipSuccess) return SLU_ERR_HIP;
+        if (hip_failed(e)) return SLU_ERR_HIP;
     }
     return SLU_OK;
 }
@@ -280,7 +287,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (!h || !device_ptr) return SLU_ERR_ARG;
     if (bytes < h->ws_bytes || ((uintptr_t)device_ptr & 255) != 0) return SLU_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    if (slu::setup_kernel_attributes() != hipSuccess) return SLU_ERR_HIP;
+    if (hip_failed(slu::setup_kernel_attributes())) return SLU_ERR_HIP;
     char *base = (char *)device_ptr;
     const slu::Analysis &an = h->an;
     hipError_t e = hipSuccess;
@@ -308,7 +315,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_rlev, an.round_levels, s);
     if (e == hipSuccess) e = upload(base, h->o_rtile, an.round_tiles, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return SLU_ERR_HIP;
+    if (hip_failed(e)) return SLU_ERR_HIP;
     slu::DevPlan &d = h->dev;
     d.slab = (double *)(base + h->o_slab);
     d.tri = (double *)(base + h->o_tri);
@@ -364,7 +371,7 @@ struct KernelTimer {
             for (int k = 0; k < 64; ++k) {
                 hipEvent_t e;
                 hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
+                if (hip_failed(err)) return err;
                 h->ev.push_back(e);
             }
         }
@@ -387,7 +394,7 @@ struct KernelTimer {
         for (size_t q = 0; q < used; q += 2) {
             float ms = 0.f;
             hipError_t e = hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]);
-            if (e != hipSuccess) return e;
+            if (hip_failed(e)) return e;
             h->kern_ms[h->ev_kind[q / 2]] += ms;
             h->kern_n[h->ev_kind[q / 2]] += 1;
         }
@@ -402,11 +409,11 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     const slu::DevPlan &d = h->dev;
 #define SLU_TIMED(kind, call)                                              \
     do {                                                                   \
-        if (kt.begin(kind) != hipSuccess) return SLU_ERR_HIP;              \
-        if ((call) != hipSuccess) return SLU_ERR_HIP;                      \
-        if (kt.end() != hipSuccess) return SLU_ERR_HIP;                    \
+        if (hip_failed(kt.begin(kind))) return SLU_ERR_HIP;              \
+        if (hip_failed((call))) return SLU_ERR_HIP;                      \
+        if (hip_failed(kt.end())) return SLU_ERR_HIP;                    \
     } while (0)
-    if (slu::launch_info_reset(d, s) != hipSuccess) return SLU_ERR_HIP;
+    if (hip_failed(slu::launch_info_reset(d, s))) return SLU_ERR_HIP;
     SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_zero(d.slab, an.slab_doubles, s));
     SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_scatter(d, values, s));
     for (const slu::WaveInfo &w : an.waves) {
@@ -437,42 +444,42 @@ int slu_factor(slu_handle *h, const double *values, void *stream) {
         // the graph reads the values from the workspace copy
         double *staged = (double *)((char *)h->ws + h->o_vals);
         if (h->an.nnz_a > 0 &&
-            hipMemcpyAsync(staged, values, (size_t)h->an.nnz_a * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            hip_failed(hipMemcpyAsync(staged, values, (size_t)h->an.nnz_a * 8, hipMemcpyDeviceToDevice, s)))
             return SLU_ERR_HIP;
         if (!h->gexec || h->graph_precision != h->precision) {
             if (h->gexec) {
                 (void)hipGraphExecDestroy(h->gexec);
                 h->gexec = nullptr;
             }
-            if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            if (!h->cap_stream && hip_failed(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)))
                 return SLU_ERR_HIP;
             hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            if (hip_failed(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)))
                 return SLU_ERR_HIP;
             KernelTimer none{h, h->cap_stream};
             const int rc = enqueue_factor(h, staged, h->cap_stream, none);
             const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
-            if (rc != SLU_OK || ec != hipSuccess) {
+            if (rc != SLU_OK || hip_failed(ec)) {
                 if (g) (void)hipGraphDestroy(g);
                 return rc != SLU_OK ? rc : SLU_ERR_HIP;
             }
             const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) {
+            if (hip_failed(ei)) {
                 h->gexec = nullptr;
                 return SLU_ERR_HIP;
             }
             h->graph_precision = h->precision;
         }
-        if (hipGraphLaunch(h->gexec, s) != hipSuccess) return SLU_ERR_HIP;
+        if (hip_failed(hipGraphLaunch(h->gexec, s))) return SLU_ERR_HIP;
     } else {
         const int rc = enqueue_factor(h, values, s, kt);
         if (rc != SLU_OK) return rc;
     }
     unsigned long long flag = 0;
-    if (hipMemcpyAsync(&flag, d.info, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess) return SLU_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
-    if (kt.collect() != hipSuccess) return SLU_ERR_HIP;
+    if (hip_failed(hipMemcpyAsync(&flag, d.info, sizeof(flag), hipMemcpyDeviceToHost, s))) return SLU_ERR_HIP;
+    if (hip_failed(hipStreamSynchronize(s))) return SLU_ERR_HIP;
+    if (hip_failed(kt.collect())) return SLU_ERR_HIP;
     if (flag != ~0ull) {
         h->zero_pivot_col = (int64_t)flag;
         return SLU_ZERO_PIVOT;
@@ -494,7 +501,7 @@ int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t 
     if (!h || nrhs < 0 || (h->an.nnz_a > 0 && !grad_values) || (nrhs > 0 && (!G || !X))) return SLU_ERR_ARG;
     if (!h->bound) return SLU_ERR_STATE;
     if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
-    if (slu::launch_value_gradient(h->dev, G, X, nrhs, ld, grad_values, (hipStream_t)stream) != hipSuccess)
+    if (hip_failed(slu::launch_value_gradient(h->dev, G, X, nrhs, ld, grad_values, (hipStream_t)stream)))
         return SLU_ERR_HIP;
     return SLU_OK;
 }
@@ -548,10 +555,10 @@ int slu_solve_refined(slu_handle *h, const double *values, const double *B, doub
                 if (!done) converged = false;
                 break;
             }
-            if (slu::launch_residual(d, values, Bc, ld, Xc, ld, R, n, nc, s) != hipSuccess) return SLU_ERR_HIP;
+            if (hip_failed(slu::launch_residual(d, values, Bc, ld, Xc, ld, R, n, nc, s))) return SLU_ERR_HIP;
             rc = solve_impl(h, R, Dv, nc, n, 0, s);
             if (rc != SLU_OK) return rc;
-            if (slu::launch_axpy(d, Xc, ld, Dv, n, nc, s) != hipSuccess) return SLU_ERR_HIP;
+            if (hip_failed(slu::launch_axpy(d, Xc, ld, Dv, n, nc, s))) return SLU_ERR_HIP;
             for (int c = 0; c < nc; ++c) prev[c] = cur[c];
             ++it;
         }
@@ -571,12 +578,11 @@ int slu_backward_error(slu_handle *h, const double *values, const double *B, con
     hipStream_t s = (hipStream_t)stream;
     for (int64_t c0 = 0; c0 < nrhs; c0 += slu::kSolveCols) {
         const int nc = (int)std::min<int64_t>(slu::kSolveCols, nrhs - c0);
-        if (slu::launch_residual_norms(h->dev, values, B + c0 * ld, X + c0 * ld, ld, nc, transpose ? 1 : 0, s) !=
-            hipSuccess)
+        if (hip_failed(slu::launch_residual_norms(h->dev, values, B + c0 * ld, X + c0 * ld, ld, nc, transpose ? 1 : 0, s)))
             return SLU_ERR_HIP;
         unsigned long long nb[64];
-        if (hipMemcpyAsync(nb, h->dev.norms, sizeof(nb), hipMemcpyDeviceToHost, s) != hipSuccess) return SLU_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
+        if (hip_failed(hipMemcpyAsync(nb, h->dev.norms, sizeof(nb), hipMemcpyDeviceToHost, s))) return SLU_ERR_HIP;
+        if (hip_failed(hipStreamSynchronize(s))) return SLU_ERR_HIP;
         double v[64];
         std::memcpy(v, nb, sizeof(v));
         for (int c = 0; c < nc; ++c) {
@@ -651,9 +657,9 @@ int slu_get_factors(const slu_handle *h, double *lval, double *uval, void *strea
     }
     hipStream_t s = (hipStream_t)stream;
     if (!slab.empty() &&
-        hipMemcpyAsync(slab.data(), h->dev.slab, slab.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        hip_failed(hipMemcpyAsync(slab.data(), h->dev.slab, slab.size() * 8, hipMemcpyDeviceToHost, s)))
         return SLU_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return SLU_ERR_HIP;
+    if (hip_failed(hipStreamSynchronize(s))) return SLU_ERR_HIP;
     for (int64_t c = 0; c < an.n; ++c) {
         const int32_t J = an.bid[c];
         const slu::LevelDev &LJ = an.levels[J];
@@ -695,6 +701,10 @@ const char *slu_error_string(int code) {
         default: return "unknown error code";
     }
 }
+
+int slu_last_hip_error(void) { return t_last_hip; }
+
+const char *slu_hip_error_string(int hip_code) { return hipGetErrorString((hipError_t)hip_code); }
 
 int slu_set_profiling(slu_handle *h, int enable) {
     if (!h) return SLU_ERR_ARG;

@@ -37,18 +37,14 @@ __device__ __forceinline__ double recip(double x) {
     return r;
 }
 
-// In-place no-pivot LU of the w x w (w <= 16) leading block of the LDS array
-// A (element (i, j) at A[j * lda + i]) by wave 0: lane i holds row i, the
-// pivot row is broadcast with readlane.  Lane j < w leaves 1 / U(j, j) in
-// rdiag[j].  The first zero / non-finite pivot is tracked with uniform
-// scalar logic in the loop and recorded in info[0] once at the end.
-__device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, int col0, double *rdiag,
-                                           unsigned long long *__restrict__ info) {
-    double v[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? A[j * lda + lane] : 0.0;
-    int bad = 16;
-    double myrd = 0.0;
+// In-place no-pivot LU of a w x w (w <= 16) block held in registers by one
+// wave: lane i < w holds row i in v[0..w) (zeros elsewhere); the pivot row
+// is broadcast with readlane.  Lane j < w ends with 1 / U(j, j) in myrd.
+// bad is the first zero / non-finite pivot (16 if none), tracked with
+// uniform scalar logic.
+__device__ __forceinline__ void lu16_regs(double (&v)[16], int w, int lane, int &bad, double &myrd) {
+    bad = 16;
+    myrd = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         if (k < w) {
@@ -67,13 +63,6 @@ __device__ __forceinline__ void lu16_wave0(double *A, int lda, int w, int lane, 
             }
         }
     }
-    if (lane < w) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (j < w) A[j * lda + lane] = v[j];
-        rdiag[lane] = myrd;
-    }
-    if (bad < 16 && lane == 0) atomicMin(info, (unsigned long long)(col0 + bad));
 }
 
 // ------------------------------------------------------------------ helpers
@@ -171,41 +160,71 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
             }
         }
     };
-    // one item per panel row (its w values) or per coupled column (its w
-    // values, contiguous in D): the loads of an item are issued together
-    for (int it = tid; it < T + nr; it += 256) {
-        double v[16];
-        if (it < T) {
-            const int row = it < w ? c0 + it : Rs[it - w];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = j < w ? D[row + (size_t)(c0 + j) * b] : 0.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (j < w) Pn[j * T + it] = v[j];
-        } else {
-            const int sI = it - T;
-            const double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = j < w ? col[j] : 0.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (j < w) Uc[sI * wu + j] = v[j];
-        }
-    }
-    // The coupled rows x coupled columns entries are not touched by steps
-    // 1 and 2, so the first round of trailing tiles is loaded now and its
-    // latency overlaps the diagonal LU, the inverses and the solves.  (A
-    // barrier waits for LDS traffic only; these loads stay in flight.)
-    if (nr > 0) load_tiles(wave);
-    __syncthreads();
-    // 1. the w x w diagonal of the chunk, factored in registers by wave 0
+    // 0/1. Wave 0 loads the chunk's w x w diagonal straight from D and
+    // factors it in registers while waves 1-3 stage the coupled part of the
+    // panel in LDS: the nr coupled rows of the chunk's columns (items
+    // [0, nr)) and the nr coupled columns of its rows (items [nr, 2 nr),
+    // contiguous in D), two items per pass so both items' loads are in
+    // flight together.  Entries past w are read at a clamped valid address
+    // and never stored.  Every wave also issues its first round of trailing
+    // tile loads (entries not touched before the trailing update), whose
+    // latency overlaps the LU and the solves; a barrier waits for LDS
+    // traffic only.
     if (wave == 0) {
-        lu16_wave0(Pn, T, w, lane, r0 + c0, const_cast<double *>(Rd), info);
+        const int lr = lane < w ? lane : 0;
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = D[c0 + lr + (size_t)(c0 + (j < w ? j : w - 1)) * b];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? v[j] : 0.0;
+        if (nr > 0) load_tiles(0);
+        int bad;
+        double myrd;
+        lu16_regs(v, w, lane, bad, myrd);
         if (lane < w) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (j < w) D[c0 + lane + (size_t)(c0 + j) * b] = Pn[j * T + lane];
+            for (int j = 0; j < 16; ++j) {
+                if (j < w) {
+                    Pn[j * T + lane] = v[j];
+                    D[c0 + lane + (size_t)(c0 + j) * b] = v[j];
+                }
+            }
+            const_cast<double *>(Rd)[lane] = myrd;
         }
+        if (bad < 16 && lane == 0) atomicMin(info, (unsigned long long)(r0 + c0 + bad));
+    } else {
+        auto load_item = [&](int it, double (&v)[16]) {
+            if (it < nr) {
+                const size_t row = (size_t)Rs[it];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = D[row + (size_t)(c0 + (j < w ? j : w - 1)) * b];
+            } else {
+                const double *__restrict__ col = D + c0 + (size_t)Rs[it - nr] * b;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = col[j < w ? j : w - 1];
+            }
+        };
+        auto store_item = [&](int it, const double (&v)[16]) {
+            if (it < nr) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) Pn[j * T + w + it] = v[j];
+            } else {
+                const int sI = it - nr;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) Uc[sI * wu + j] = v[j];
+            }
+        };
+        for (int it = tid - 64; it < 2 * nr; it += 384) {
+            const int it2 = it + 192;
+            double v[16], v2[16];
+            load_item(it, v);
+            if (it2 < 2 * nr) load_item(it2, v2);
+            store_item(it, v);
+            if (it2 < 2 * nr) store_item(it2, v2);
+        }
+        if (nr > 0) load_tiles(wave);
     }
     __syncthreads();
     // 2. coupled rows (x U_cc = a) and coupled columns (L_cc y = a): one

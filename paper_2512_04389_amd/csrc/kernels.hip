@@ -140,7 +140,11 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     double4_t acc[8];
     bool vr[8];
     size_t rowo[8];
+    // The coupled-row indices of a round are read from LDS first, all
+    // together, and only then are the 32 loads issued: interleaved, every
+    // load would wait for its own LDS read.
     auto load_tiles = [&](int q0) {
+        int cix[8][4];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int q = q0 + 4 * u;
@@ -149,16 +153,21 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
             const int ra = 16 * ti + li;
             vr[u] = q < ntiles && ra < nr;
             rowo[u] = (size_t)Rs[ra < nr ? ra : nr - 1];
-            // entries outside the coupled set read a clamped valid address;
-            // an MFMA output element depends only on its own accumulator
-            // input and those elements are never stored, so no select is
-            // needed (it would make each load wait at once)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int sc = 16 * tj + lk + 4 * r;
-                acc[u][r] = D[rowo[u] + (size_t)Rs[sc < nr ? sc : nr - 1] * b];
+                cix[u][r] = Rs[sc < nr ? sc : nr - 1];
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
+        // entries outside the coupled set read a clamped valid address; an
+        // MFMA output element depends only on its own accumulator input and
+        // those elements are never stored, so no select is needed (it would
+        // make each load wait at once)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[u][r] = D[rowo[u] + (size_t)cix[u][r] * b];
     };
     // 0/1. Wave 0 loads the chunk's w x w diagonal straight from D and
     // factors it in registers while waves 1-3 stage the coupled part of the
@@ -175,12 +184,25 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
         double v[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) v[j] = D[c0 + lr + (size_t)(c0 + (j < w ? j : w - 1)) * b];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? v[j] : 0.0;
-        if (nr > 0) load_tiles(0);
+        // the diagonal's loads go out first, then the tile loads; the LU
+        // waits for the former only.  (The LU is written out in both arms so
+        // the wait counts stay exact: after a join the compiler would wait
+        // as if the tile loads had been issued on the path without them.)
         int bad;
         double myrd;
-        lu16_regs(v, w, lane, bad, myrd);
+        auto lu = [&]() {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? v[j] : 0.0;
+            lu16_regs(v, w, lane, bad, myrd);
+        };
+        if (nr > 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            load_tiles(0);
+            __builtin_amdgcn_sched_barrier(0);
+            lu();
+        } else {
+            lu();
+        }
         if (lane < w) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {

@@ -315,21 +315,35 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 const int ar = 16 * ti + li;
                 const int scc = sc < nr ? sc : nr - 1, arc = ar < nr ? ar : nr - 1;
                 const bool va = ar < nr, vcc = sc < nr;
+                // every LDS read of the tile (operands, store columns) is
+                // issued before its MFMAs, so they wait once
+                double al[4], bl[4];
+                int cs[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    const int kc = k < w ? k : 0;
+                    al[kk] = Uc[scc * wu + kc];
+                    bl[kk] = Pn[kc * T + w + arc];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int sc2 = 16 * tj + lk + 4 * r;
+                    cs[r] = Rs[sc2 < nr ? sc2 : nr - 1];
+                }
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = 4 * kk + lk;
                     if (4 * kk < w) {
-                        const int kc = k < w ? k : 0;
-                        const double al = Uc[scc * wu + kc], bl = Pn[kc * T + w + arc];
-                        const double a = (k < w && vcc) ? -al : 0.0;   // (U^T)[sc][k]
-                        const double bv = (k < w && va) ? bl : 0.0;    // (L^T)[k][ar]
+                        const double a = (k < w && vcc) ? -al[kk] : 0.0;   // (U^T)[sc][k]
+                        const double bv = (k < w && va) ? bl[kk] : 0.0;    // (L^T)[k][ar]
                         acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int sc2 = 16 * tj + lk + 4 * r;
-                    if (vr[u] && sc2 < nr) D[rowo[u] + (size_t)Rs[sc2] * b] = acc[u][r];
+                    if (vr[u] && sc2 < nr) D[rowo[u] + (size_t)cs[r] * b] = acc[u][r];
                 }
             }
         }

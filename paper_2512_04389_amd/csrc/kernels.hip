@@ -28,6 +28,25 @@ __device__ __forceinline__ double bcast_lane(double v, int k) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Value of lane J of each 16-lane row in every lane of that row (DPP
+// row_newbcast, two 32-bit moves).
+template <int J>
+__device__ __forceinline__ double bcast16(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x150 + J, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x150 + J, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value of v in lane src of the wave, per lane (LDS crossbar permute, no LDS
+// memory; every lane of the wave must be active).
+__device__ __forceinline__ double perm_lane(double v, int src) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)x);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 1 / x in FP64: hardware estimate refined by two Newton steps (relative
 // error within a few ulps; used where a pivot's reciprocal scales a column).
 __device__ __forceinline__ double recip(double x) {
@@ -37,32 +56,41 @@ __device__ __forceinline__ double recip(double x) {
     return r;
 }
 
-// In-place no-pivot LU of a w x w (w <= 16) block held in registers by one
-// wave: lane i < w holds row i in v[0..w) (zeros elsewhere); the pivot row
-// is broadcast with readlane.  Lane j < w ends with 1 / U(j, j) in myrd.
-// bad is the first zero / non-finite pivot (16 if none), tracked with
-// uniform scalar logic.
-__device__ __forceinline__ void lu16_regs(double (&v)[16], int w, int lane, int &bad, double &myrd) {
-    bad = 16;
-    myrd = 0.0;
+// In-place no-pivot LU of a w x w (w <= 16) block held by one wave in a 2D
+// layout: lane i + 16 g holds a[s] = A(i, 4 g + s) (zeros outside w x w).
+// Pivot k: its value by readlane, the pivot row to every lane of each
+// 16-lane row by DPP row broadcast, the multipliers of column k from its
+// column group to the other groups by a lane permute; each lane then
+// updates its four entries.  Lane k of group 0 ends with 1 / U(k, k) in
+// myrd; bad is the first zero / non-finite pivot (16 if none), uniform.
+template <int K>
+__device__ __forceinline__ void lu16_step(double (&a)[4], int i, int g, int w, int &bad, double &myrd) {
+    if (K < w) {
+        constexpr int g0 = K >> 2, s0 = K & 3;
+        const double piv = bcast_lane(a[s0], K + 16 * g0);
+        if (!(piv != 0.0 && isfinite(piv))) bad = min(bad, K);
+        const double rp = recip(piv);
+        myrd = (i == K && g == 0) ? rp : myrd;
+        const double lg = a[s0] * rp;
+        if (g == g0 && i > K) a[s0] = lg;
+        const double l = perm_lane(lg, i + 16 * g0);
+        double u[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k < w) {
-            double u[16];
+        for (int s = 0; s < 4; ++s) u[s] = bcast16<K>(a[s]);
 #pragma unroll
-            for (int j = k; j < 16; ++j) u[j] = bcast_lane(v[j], k);
-            const double piv = u[k];
-            if (!(piv != 0.0 && isfinite(piv))) bad = min(bad, k);
-            const double rp = recip(piv);
-            myrd = (lane == k) ? rp : myrd;
-            if (lane > k) {
-                const double l = v[k] * rp;
-                v[k] = l;
-#pragma unroll
-                for (int j = k + 1; j < 16; ++j) v[j] -= l * u[j];
-            }
+        for (int s = 0; s < 4; ++s) {
+            const bool upd = i > K && 4 * g + s > K;
+            const double nv = a[s] - l * u[s];
+            a[s] = upd ? nv : a[s];
         }
     }
+    if constexpr (K + 1 < 16) lu16_step<K + 1>(a, i, g, w, bad, myrd);
+}
+
+__device__ __forceinline__ void lu16_2d(double (&a)[4], int w, int lane, int &bad, double &myrd) {
+    bad = 16;
+    myrd = 0.0;
+    lu16_step<0>(a, lane & 15, lane >> 4, w, bad, myrd);
 }
 
 // ------------------------------------------------------------------ helpers
@@ -180,10 +208,15 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     // latency overlaps the LU and the solves; a barrier waits for LDS
     // traffic only.
     if (wave == 0) {
-        const int lr = lane < w ? lane : 0;
-        double v[16];
+        // 2D layout: lane gi + 16 gg holds D(c0 + gi, c0 + 4 gg + s)
+        const int gi = lane & 15, gg = lane >> 4;
+        const int gic = gi < w ? gi : w - 1;
+        double a[4];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = D[c0 + lr + (size_t)(c0 + (j < w ? j : w - 1)) * b];
+        for (int s = 0; s < 4; ++s) {
+            const int j = 4 * gg + s;
+            a[s] = D[c0 + gic + (size_t)(c0 + (j < w ? j : w - 1)) * b];
+        }
         // the diagonal's loads go out first, then the tile loads; the LU
         // waits for the former only.  (The LU is written out in both arms so
         // the wait counts stay exact: after a join the compiler would wait
@@ -192,8 +225,8 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
         double myrd;
         auto lu = [&]() {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = (j < w && lane < w) ? v[j] : 0.0;
-            lu16_regs(v, w, lane, bad, myrd);
+            for (int s = 0; s < 4; ++s) a[s] = (4 * gg + s < w && gi < w) ? a[s] : 0.0;
+            lu16_2d(a, w, lane, bad, myrd);
         };
         if (nr > 0) {
             __builtin_amdgcn_sched_barrier(0);
@@ -203,15 +236,16 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
         } else {
             lu();
         }
-        if (lane < w) {
+        if (gi < w) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int s = 0; s < 4; ++s) {
+                const int j = 4 * gg + s;
                 if (j < w) {
-                    Pn[j * T + lane] = v[j];
-                    D[c0 + lane + (size_t)(c0 + j) * b] = v[j];
+                    Pn[j * T + gi] = a[s];
+                    D[c0 + gi + (size_t)(c0 + j) * b] = a[s];
                 }
             }
-            const_cast<double *>(Rd)[lane] = myrd;
+            if (gg == 0) const_cast<double *>(Rd)[gi] = myrd;
         }
         if (bad < 16 && lane == 0) atomicMin(info, (unsigned long long)(r0 + c0 + bad));
     } else {
@@ -1024,15 +1058,6 @@ hipError_t launch_scatter_perm(const DevPlan &d, double *X, int64_t ld, int nc, 
 }
 
 // ------------------------------------------------- triangular solves in D_i
-// Value of lane J of each 16-lane row in every lane of that row (DPP
-// row_newbcast, two 32-bit moves).
-template <int J>
-__device__ __forceinline__ double bcast16(double v) {
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x150 + J, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x150 + J, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Forward substitution with a w x w lower triangle F held by the 16 lanes of
 // a row: lane i has x_i and its row f[j] = F(i, j); diagonal scaled by dinv

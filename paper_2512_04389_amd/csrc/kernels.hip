@@ -651,7 +651,7 @@ hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // triangle operands of a step (the inverted diagonal tile and the wave's
 // first kPanelPf update tiles) are loaded one step ahead, so their latency
 // overlaps the previous step instead of stalling the MFMA chains.
-constexpr int kPanelPf = 6;
+constexpr int kPanelPf = 6;   // even: the tiles are taken two at a time
 
 size_t panel_tables_bytes(int max_kp) {
     const size_t ntm = (size_t)(max_kp >> 4);
@@ -751,48 +751,65 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) ubc[i][kk] = ubn[i][kk];
         fetch(c + 1);
-        double4_t acc = {0, 0, 0, 0};
+        // diagonal tile of the wave's own 16 rows (read and written by this
+        // wave only, so no barrier between the product and its store)
         if (wave < NH) {
-            const int h = wave;
+            double4_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int k = 4 * kk + lk;
-                const double a = ld_x(16 * c + k, 16 * h + li);
+                const double a = ld_x(16 * c + k, 16 * wave + li);
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tbc[kk], acc, 0, 0, 0);
             }
-        }
-        __syncthreads();
-        if (wave < NH) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) st_x(16 * c + li, 16 * wave + lk + 4 * r, acc[r]);
         }
         __syncthreads();
         const int q0 = SP(c), ntq = (SP(c + 1) - q0) * NH;
-        auto update = [&](int q, const double (&bv)[4]) {
-            const int cc = SX(q0 + q / NH);
-            const int h = q % NH;
-            double4_t u;
+        // two update tiles of the wave at a time (distinct columns cc), so
+        // their MFMA chains interleave; without a second tile the first is
+        // computed twice and stored once
+        auto update2 = [&](int qa, const double (&bva)[4], int qb, const double (&bvb)[4], bool hasb) {
+            const int qs[2] = {qa, hasb ? qb : qa};
+            int cc[2], hh[2];
+            double4_t u[2];
+            double a[2][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) u[r] = ld_x(16 * cc + li, 16 * h + lk + 4 * r);
+            for (int t = 0; t < 2; ++t) {
+                cc[t] = SX(q0 + qs[t] / NH);
+                hh[t] = qs[t] % NH;
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const double a = -ld_x(16 * c + 4 * kk + lk, 16 * h + li);
-                u = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[kk], u, 0, 0, 0);
+                for (int r = 0; r < 4; ++r) u[t][r] = ld_x(16 * cc[t] + li, 16 * hh[t] + lk + 4 * r);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) a[t][kk] = -ld_x(16 * c + 4 * kk + lk, 16 * hh[t] + li);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) st_x(16 * cc + li, 16 * h + lk + 4 * r, u[r]);
+            for (int kk = 0; kk < 4; ++kk) {
+                u[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][kk], bva[kk], u[0], 0, 0, 0);
+                u[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][kk], bvb[kk], u[1], 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) st_x(16 * cc[0] + li, 16 * hh[0] + lk + 4 * r, u[0][r]);
+            if (hasb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) st_x(16 * cc[1] + li, 16 * hh[1] + lk + 4 * r, u[1][r]);
+            }
         };
 #pragma unroll
-        for (int i = 0; i < kPanelPf; ++i) {
+        for (int i = 0; i < kPanelPf; i += 2) {
             const int q = wave + 4 * i;
-            if (q < ntq) update(q, ubc[i]);
+            if (q < ntq) update2(q, ubc[i], q + 4, ubc[i + 1], q + 4 < ntq);
         }
-        for (int q = wave + 4 * kPanelPf; q < ntq; q += 4) {
-            const int cc = SX(q0 + q / NH);
-            double bv[4];
+        for (int q = wave + 4 * kPanelPf; q < ntq; q += 8) {
+            const bool hasb = q + 4 < ntq;
+            const int cca = SX(q0 + q / NH), ccb = SX(q0 + (hasb ? q + 4 : q) / NH);
+            double bva[4], bvb[4];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) bv[kk] = T[(size_t)(16 * c + 4 * kk + lk) * kp + 16 * cc + li];
-            update(q, bv);
+            for (int kk = 0; kk < 4; ++kk) {
+                bva[kk] = T[(size_t)(16 * c + 4 * kk + lk) * kp + 16 * cca + li];
+                bvb[kk] = T[(size_t)(16 * c + 4 * kk + lk) * kp + 16 * ccb + li];
+            }
+            update2(q, bva, q + 4, bvb, hasb);
         }
         __syncthreads();
     }

@@ -69,6 +69,7 @@ struct WaveInfo {
     int32_t begin, end;         // range in wave_levels
     int32_t lds_getrf;          // dynamic LDS bytes of the GETRF launch
     int32_t max_nt;             // largest kp / 16
+    int32_t max_tslots;         // largest kp / 16 + structurally nonzero off-diagonal tiles
     int32_t max_m;              // largest panel row count
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;

@@ -421,7 +421,7 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         const int32_t *lv = d.wave_levels + w.begin;
         SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
         if (w.max_m > 0 && w.max_kp > 0) {
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, nlev, w.max_nt, s));
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, nlev, w.max_tslots, s));
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
         }
         for (int r = w.round_begin; r < w.round_end; ++r)

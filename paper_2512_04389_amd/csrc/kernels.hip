@@ -562,58 +562,62 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 }
 
 // ------------------------------------------- compact coupled triangles
-// One workgroup per tile row tr of the compact triangles (see LevelDev):
-// copies rows [16 tr, 16 tr + 16) of Tu = U_ii[K, K] and Tl = L_ii[K, K]^T
-// from the factored diagonal block, then inverts the two diagonal tiles
-// (back substitution per column, FP64 divisions by the pivots).
+// One workgroup per 16 x 16 tile that the panel solves read: the nt
+// diagonal tiles, then the structurally nonzero tiles of the level's tile
+// rows (trow).  A thread copies one element of Tu = U_ii[K, K] and one of
+// Tl = L_ii[K, K]^T from the factored diagonal block; a diagonal tile's
+// workgroup then inverts its two triangles (back substitution per column,
+// FP64 divisions by the pivots).  Tiles outside these lists are never
+// written and never read.
 __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ slab, double *__restrict__ tri,
                                                     const LevelDev *__restrict__ levels,
                                                     const int32_t *__restrict__ lvl,
-                                                    const int32_t *__restrict__ Kidx) {
+                                                    const int32_t *__restrict__ Kidx,
+                                                    const int32_t *__restrict__ trow_ptr,
+                                                    const int32_t *__restrict__ trow_idx) {
     __shared__ double du[16][17], dl[16][17];
     const LevelDev L = levels[lvl[blockIdx.y]];
     const int kp = L.kp, kap = L.kappa, b = L.b, nt = kp >> 4;
-    const int tr = blockIdx.x;
-    if (tr >= nt) return;
+    const int32_t *__restrict__ tptr = trow_ptr + L.trow;
+    const int slot = blockIdx.x;
+    if (nt == 0) return;
+    const int tb = tptr[0];
+    if (slot >= nt + (tptr[nt] - tb)) return;
+    int tr, tc;
+    if (slot < nt) {
+        tr = tc = slot;
+    } else {
+        // tile row of off-diagonal tile e: the last row r with tptr[r] - tb <= e
+        const int e = slot - nt;
+        tc = trow_idx[tb + e];
+        int lo = 0, hi = nt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tptr[mid] - tb <= e) lo = mid; else hi = mid - 1;
+        }
+        tr = lo;
+    }
     const double *__restrict__ D = slab + L.offD;
     const int32_t *__restrict__ K = Kidx + L.Koff;
     double *__restrict__ Tu = tri + L.offT;
     double *__restrict__ Tl = Tu + (size_t)kp * kp;
     double *__restrict__ Iu = Tl + (size_t)kp * kp;
     double *__restrict__ Il = Iu + (size_t)nt * 256;
-    const int width = kp - 16 * tr;
-    // thread (column cc, row rr): column index K[t2] from global once, then
-    // the 16 rows' values of U and L^T issued together
-    for (int cc = threadIdx.x; cc < width; cc += 256) {
-        const int t2 = 16 * tr + cc;
-        const bool c_in = t2 < kap;
-        const size_t k2 = c_in ? (size_t)K[t2] : 0;
-        double u[16], lt[16];
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            const int t1 = 16 * tr + rr;
-            const bool in = c_in && t1 < kap;
-            const size_t k1 = in ? (size_t)K[t1] : 0;
-            u[rr] = (in && t1 <= t2) ? D[k1 + k2 * b] : 0.0;
-            lt[rr] = (in && t1 < t2) ? D[k2 + k1 * b] : 0.0;
-        }
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            const int t1 = 16 * tr + rr;
-            const bool in = c_in && t1 < kap;
-            double uu = u[rr], ll = lt[rr];
-            if (t1 == t2) {
-                ll = 1.0;
-                if (!in) uu = 1.0;
-            }
-            Tu[(size_t)t1 * kp + t2] = uu;
-            Tl[(size_t)t1 * kp + t2] = ll;
-            if (cc < 16) {
-                du[rr][cc] = uu;
-                dl[rr][cc] = ll;
-            }
-        }
+    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+    const int t1 = 16 * tr + rr, t2 = 16 * tc + cc;
+    const bool in = t1 < kap && t2 < kap;
+    const size_t k1 = in ? (size_t)K[t1] : 0, k2 = in ? (size_t)K[t2] : 0;
+    double uu = (in && t1 <= t2) ? D[k1 + k2 * b] : 0.0;
+    double ll = (in && t1 < t2) ? D[k2 + k1 * b] : 0.0;
+    if (t1 == t2) {
+        ll = 1.0;
+        if (!in) uu = 1.0;
     }
+    Tu[(size_t)t1 * kp + t2] = uu;
+    Tl[(size_t)t1 * kp + t2] = ll;
+    if (slot >= nt) return;
+    du[rr][cc] = uu;
+    dl[rr][cc] = ll;
     __syncthreads();
     if (threadIdx.x < 32) {
         const int j = threadIdx.x & 15;
@@ -632,10 +636,10 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
     }
 }
 
-hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s) {
-    if (max_nt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)max_nt, (unsigned)nlev), dim3(256), 0, s, d.slab, d.tri,
-                       d.levels, lvl, d.K_idx);
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_slots, hipStream_t s) {
+    if (max_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)max_slots, (unsigned)nlev), dim3(256), 0, s, d.slab, d.tri,
+                       d.levels, lvl, d.K_idx, d.trow_ptr, d.trow_idx);
     return hipGetLastError();
 }
 

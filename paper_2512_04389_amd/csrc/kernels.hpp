@@ -57,7 +57,8 @@ hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);
 hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
 hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s);
-hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_nt, hipStream_t s);
+// max_slots: largest count of triangle tiles a level of the wave reads.
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_slots, hipStream_t s);
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s);
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s);

@@ -645,7 +645,8 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 const int32_t lds = L.b <= kLdsDenseMax ? (int32_t)((int64_t)L.b * (L.b | 1) * 8) : L.lds_getrf;
                 w.lds_getrf = std::max(w.lds_getrf, lds);
                 w.max_nt = std::max(w.max_nt, L.kp / 16);
-                w.max_tslots = std::max(w.max_tslots, L.kp / 16 + an.trow_ptr[L.trow + L.kp / 16] - an.trow_ptr[L.trow]);
+                an.tslot_off.push_back(w.tslots);
+                w.tslots += L.kp / 16 + an.trow_ptr[L.trow + L.kp / 16] - an.trow_ptr[L.trow];
                 w.max_kp = std::max(w.max_kp, L.kp);
                 w.max_m = std::max(w.max_m, L.m);
                 w.max_b = std::max(w.max_b, L.b);

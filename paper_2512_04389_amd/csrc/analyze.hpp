@@ -69,7 +69,7 @@ struct WaveInfo {
     int32_t begin, end;         // range in wave_levels
     int32_t lds_getrf;          // dynamic LDS bytes of the GETRF launch
     int32_t max_nt;             // largest kp / 16
-    int32_t max_tslots;         // largest kp / 16 + structurally nonzero off-diagonal tiles
+    int32_t tslots;             // triangle tiles read by the wave's panel solves (all levels)
     int32_t max_m;              // largest panel row count
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
@@ -122,6 +122,7 @@ struct Analysis {
     std::vector<RoundInfo> rounds;
     std::vector<int32_t> round_levels;   // levels of every round, consecutive
     std::vector<int64_t> round_tiles;    // first SSSSM workgroup of each level within its round
+    std::vector<int32_t> tslot_off;      // per wave_levels entry: first triangle-gather workgroup of the level in its wave
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
     std::vector<int32_t> trow_idx;
     int64_t tri_doubles = 0;

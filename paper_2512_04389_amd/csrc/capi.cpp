@@ -17,7 +17,7 @@ struct slu_handle {
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
     size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
-        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_rlev, o_rtile, o_info, o_scratch, o_ir, o_norms, o_vals;
+        o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_rlev, o_rtile, o_tsoff, o_info, o_scratch, o_ir, o_norms, o_vals;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
     std::vector<int64_t> at_vidx;
@@ -84,6 +84,7 @@ void plan_workspace(slu_handle *h) {
     h->o_wlev = take(an.wave_levels.size() * 4);
     h->o_rlev = take(an.round_levels.size() * 4);
     h->o_rtile = take(an.round_tiles.size() * 8);
+    h->o_tsoff = take(an.tslot_off.size() * 4);
     h->o_info = take(64);
     h->o_scratch = take((size_t)an.n * slu::kSolveCols * 8);
     h->o_ir = take((size_t)2 * an.n * slu::kSolveCols * 8);
@@ -314,6 +315,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     if (e == hipSuccess) e = upload(base, h->o_wlev, an.wave_levels, s);
     if (e == hipSuccess) e = upload(base, h->o_rlev, an.round_levels, s);
     if (e == hipSuccess) e = upload(base, h->o_rtile, an.round_tiles, s);
+    if (e == hipSuccess) e = upload(base, h->o_tsoff, an.tslot_off, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (hip_failed(e)) return SLU_ERR_HIP;
     slu::DevPlan &d = h->dev;
@@ -342,6 +344,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.wave_levels = (const int32_t *)(base + h->o_wlev);
     d.round_levels = (const int32_t *)(base + h->o_rlev);
     d.round_tiles = (const int64_t *)(base + h->o_rtile);
+    d.tslot_off = (const int32_t *)(base + h->o_tsoff);
     d.info = (unsigned long long *)(base + h->o_info);
     d.scratch = (double *)(base + h->o_scratch);
     d.ir = (double *)(base + h->o_ir);
@@ -421,7 +424,7 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         const int32_t *lv = d.wave_levels + w.begin;
         SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
         if (w.max_m > 0 && w.max_kp > 0) {
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, nlev, w.max_tslots, s));
+            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
         }
         for (int r = w.round_begin; r < w.round_end; ++r)

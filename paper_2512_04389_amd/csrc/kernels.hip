@@ -562,9 +562,10 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 }
 
 // ------------------------------------------- compact coupled triangles
-// One workgroup per 16 x 16 tile that the panel solves read: the nt
-// diagonal tiles, then the structurally nonzero tiles of the level's tile
-// rows (trow).  A thread copies one element of Tu = U_ii[K, K] and one of
+// One workgroup per 16 x 16 tile that the panel solves read, numbered over
+// the wave's levels (soff: first workgroup of each level): per level the nt
+// diagonal tiles, then the structurally nonzero tiles of its tile rows
+// (trow).  A thread copies one element of Tu = U_ii[K, K] and one of
 // Tl = L_ii[K, K]^T from the factored diagonal block; a diagonal tile's
 // workgroup then inverts its two triangles (back substitution per column,
 // FP64 divisions by the pivots).  Tiles outside these lists are never
@@ -572,14 +573,22 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ slab, double *__restrict__ tri,
                                                     const LevelDev *__restrict__ levels,
                                                     const int32_t *__restrict__ lvl,
+                                                    const int32_t *__restrict__ soff, int nlev,
                                                     const int32_t *__restrict__ Kidx,
                                                     const int32_t *__restrict__ trow_ptr,
                                                     const int32_t *__restrict__ trow_idx) {
     __shared__ double du[16][17], dl[16][17];
-    const LevelDev L = levels[lvl[blockIdx.y]];
+    // the level of this workgroup: the last one whose first slot is <= it
+    const int bid = blockIdx.x;
+    int lo = 0, hi = nlev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (soff[mid] <= bid) lo = mid; else hi = mid - 1;
+    }
+    const LevelDev L = levels[lvl[lo]];
     const int kp = L.kp, kap = L.kappa, b = L.b, nt = kp >> 4;
     const int32_t *__restrict__ tptr = trow_ptr + L.trow;
-    const int slot = blockIdx.x;
+    const int slot = bid - soff[lo];
     if (nt == 0) return;
     const int tb = tptr[0];
     if (slot >= nt + (tptr[nt] - tb)) return;
@@ -590,12 +599,12 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
         // tile row of off-diagonal tile e: the last row r with tptr[r] - tb <= e
         const int e = slot - nt;
         tc = trow_idx[tb + e];
-        int lo = 0, hi = nt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tptr[mid] - tb <= e) lo = mid; else hi = mid - 1;
+        int rlo = 0, rhi = nt - 1;
+        while (rlo < rhi) {
+            const int mid = (rlo + rhi + 1) >> 1;
+            if (tptr[mid] - tb <= e) rlo = mid; else rhi = mid - 1;
         }
-        tr = lo;
+        tr = rlo;
     }
     const double *__restrict__ D = slab + L.offD;
     const int32_t *__restrict__ K = Kidx + L.Koff;
@@ -636,10 +645,11 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
     }
 }
 
-hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_slots, hipStream_t s) {
-    if (max_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)max_slots, (unsigned)nlev), dim3(256), 0, s, d.slab, d.tri,
-                       d.levels, lvl, d.K_idx, d.trow_ptr, d.trow_idx);
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const int32_t *soff, int nlev, int slots,
+                                  hipStream_t s) {
+    if (slots <= 0 || nlev <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tri_gather, dim3((unsigned)slots), dim3(256), 0, s, d.slab, d.tri, d.levels, lvl, soff, nlev,
+                       d.K_idx, d.trow_ptr, d.trow_idx);
     return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct DevPlan {
     const int32_t *wave_levels; // levels of every wave, consecutive
     const int32_t *round_levels;
     const int64_t *round_tiles;
+    const int32_t *tslot_off;   // first triangle-gather workgroup of every level in its wave
     unsigned long long *info;   // [0] smallest failed pivot column (or ~0)
     double *scratch;            // n * kSolveCols doubles
     double *ir;                 // 2 * n * kSolveCols doubles: refinement residual and correction
@@ -57,8 +58,9 @@ hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);
 hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
 hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s);
-// max_slots: largest count of triangle tiles a level of the wave reads.
-hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_slots, hipStream_t s);
+// soff: first workgroup of each of the wave's levels; slots: their total.
+hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const int32_t *soff, int nlev, int slots,
+                                  hipStream_t s);
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s);
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s);

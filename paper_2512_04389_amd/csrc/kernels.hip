@@ -661,17 +661,6 @@ hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const in
 // (inverted diagonal tile), then X_c' -= X_c T_cc' for the structurally
 // nonzero tiles c' > c.  Every product is a 16 x 16 x 16 FP64 MFMA block.
 // The rows live in LDS when RT x kp doubles fit, else in the panel itself.
-// The level's tile lists are staged in LDS after the rows, and the
-// triangle operands of a step (the inverted diagonal tile and the wave's
-// first kPanelPf update tiles) are loaded one step ahead, so their latency
-// overlaps the previous step instead of stalling the MFMA chains.
-constexpr int kPanelPf = 6;   // even: the tiles are taken two at a time
-
-size_t panel_tables_bytes(int max_kp) {
-    const size_t ntm = (size_t)(max_kp >> 4);
-    return (ntm + 1 + ntm * (ntm + 1) / 2) * sizeof(int32_t);
-}
-
 template <int RT, bool IN_LDS>
 __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, const double *__restrict__ tri,
                                                      const LevelDev *__restrict__ levels,
@@ -723,107 +712,42 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
                 if (t < kp) xs_lds[t * LD + r] = (r < nrow && t < kap) ? v[u] : 0.0;
             }
         }
+        __syncthreads();
     }
-    // tile lists: SP(0..nt) row pointers (rebased), SX() tile columns,
-    // staged in LDS after the rows (read from global memory when the rows
-    // themselves do not fit in LDS)
-    int *sp = (int *)(xs_lds + (IN_LDS ? (size_t)kp * LD : 0));
-    const int tb = tptr[0];
-    const int ntile = tptr[nt] - tb;
-    int *sx = sp + nt + 1;
-    if (IN_LDS) {
-        for (int e = tid; e <= nt; e += 256) sp[e] = tptr[e] - tb;
-        for (int e = tid; e < ntile; e += 256) sx[e] = trow_idx[tb + e];
-    }
-    __syncthreads();
-    auto SP = [&](int e) -> int { return IN_LDS ? sp[e] : tptr[e] - tb; };
-    auto SX = [&](int e) -> int { return IN_LDS ? sx[e] : trow_idx[tb + e]; };
-    // operands of step c: the diagonal inverse and the wave's update tiles
-    // q = wave + 4 i (i < kPanelPf); every load is issued, from a clamped
-    // valid address, so the wait counts stay exact
-    double tbn[4], ubn[kPanelPf][4];
-    auto fetch = [&](int c) {
-        const int cq = c < nt ? c : nt - 1;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) tbn[kk] = Tinv[(size_t)cq * 256 + (4 * kk + lk) * 16 + li];
-        const int q0 = SP(cq), ntq = (SP(cq + 1) - q0) * NH;
-#pragma unroll
-        for (int i = 0; i < kPanelPf; ++i) {
-            const int q = wave + 4 * i;
-            const int cc = ntq > 0 ? SX(q0 + (q < ntq ? q : ntq - 1) / NH) : cq;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) ubn[i][kk] = T[(size_t)(16 * cq + 4 * kk + lk) * kp + 16 * cc + li];
-        }
-    };
-    fetch(0);
     for (int c = 0; c < nt; ++c) {
-        double tbc[4], ubc[kPanelPf][4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) tbc[kk] = tbn[kk];
-#pragma unroll
-        for (int i = 0; i < kPanelPf; ++i)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) ubc[i][kk] = ubn[i][kk];
-        fetch(c + 1);
-        // diagonal tile of the wave's own 16 rows (read and written by this
-        // wave only, so no barrier between the product and its store)
+        double4_t acc = {0, 0, 0, 0};
         if (wave < NH) {
-            double4_t acc = {0, 0, 0, 0};
+            const int h = wave;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int k = 4 * kk + lk;
-                const double a = ld_x(16 * c + k, 16 * wave + li);
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tbc[kk], acc, 0, 0, 0);
+                const double a = ld_x(16 * c + k, 16 * h + li);
+                const double bv = Tinv[(size_t)c * 256 + k * 16 + li];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
             }
+        }
+        __syncthreads();
+        if (wave < NH) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) st_x(16 * c + li, 16 * wave + lk + 4 * r, acc[r]);
         }
         __syncthreads();
-        const int q0 = SP(c), ntq = (SP(c + 1) - q0) * NH;
-        // two update tiles of the wave at a time (distinct columns cc), so
-        // their MFMA chains interleave; without a second tile the first is
-        // computed twice and stored once
-        auto update2 = [&](int qa, const double (&bva)[4], int qb, const double (&bvb)[4], bool hasb) {
-            const int qs[2] = {qa, hasb ? qb : qa};
-            int cc[2], hh[2];
-            double4_t u[2];
-            double a[2][4];
+        const int q0 = tptr[c], q1 = tptr[c + 1];
+        for (int q = wave; q < (q1 - q0) * NH; q += 4) {
+            const int cc = trow_idx[q0 + q / NH];
+            const int h = q % NH;
+            double4_t u;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                cc[t] = SX(q0 + qs[t] / NH);
-                hh[t] = qs[t] % NH;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) u[t][r] = ld_x(16 * cc[t] + li, 16 * hh[t] + lk + 4 * r);
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) a[t][kk] = -ld_x(16 * c + 4 * kk + lk, 16 * hh[t] + li);
-            }
+            for (int r = 0; r < 4; ++r) u[r] = ld_x(16 * cc + li, 16 * h + lk + 4 * r);
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                u[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][kk], bva[kk], u[0], 0, 0, 0);
-                u[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][kk], bvb[kk], u[1], 0, 0, 0);
+                const int k = 4 * kk + lk;
+                const double a = -ld_x(16 * c + k, 16 * h + li);
+                const double bv = T[(size_t)(16 * c + k) * kp + 16 * cc + li];
+                u = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, u, 0, 0, 0);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) st_x(16 * cc[0] + li, 16 * hh[0] + lk + 4 * r, u[0][r]);
-            if (hasb) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) st_x(16 * cc[1] + li, 16 * hh[1] + lk + 4 * r, u[1][r]);
-            }
-        };
-#pragma unroll
-        for (int i = 0; i < kPanelPf; i += 2) {
-            const int q = wave + 4 * i;
-            if (q < ntq) update2(q, ubc[i], q + 4, ubc[i + 1], q + 4 < ntq);
-        }
-        for (int q = wave + 4 * kPanelPf; q < ntq; q += 8) {
-            const bool hasb = q + 4 < ntq;
-            const int cca = SX(q0 + q / NH), ccb = SX(q0 + (hasb ? q + 4 : q) / NH);
-            double bva[4], bvb[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                bva[kk] = T[(size_t)(16 * c + 4 * kk + lk) * kp + 16 * cca + li];
-                bvb[kk] = T[(size_t)(16 * c + 4 * kk + lk) * kp + 16 * ccb + li];
-            }
-            update2(q, bva, q + 4, bvb, hasb);
+            for (int r = 0; r < 4; ++r) st_x(16 * cc + li, 16 * h + lk + 4 * r, u[r]);
         }
         __syncthreads();
     }
@@ -838,8 +762,7 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                    hipStream_t s) {
     if (max_m <= 0 || max_kp <= 0) return hipSuccess;
-    const size_t tab = panel_tables_bytes(max_kp);
-    const size_t lds32 = (size_t)33 * max_kp * sizeof(double) + tab, lds16 = (size_t)17 * max_kp * sizeof(double) + tab;
+    const size_t lds32 = (size_t)33 * max_kp * sizeof(double), lds16 = (size_t)17 * max_kp * sizeof(double);
     if (lds32 <= 150 * 1024) {
         dim3 grid((unsigned)((max_m + 31) / 32), 2, (unsigned)nlev);
         hipLaunchKernelGGL((k_panel_solve<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, lvl,

@@ -1038,37 +1038,41 @@ __global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restric
     const int li = lane & 15, lk = lane >> 4;
     const int wr = TT == 64 ? wave >> 1 : 0, wc = TT == 64 ? wave & 1 : 0;
 
-    // epilogue addressing, loaded first so that its latency overlaps the
-    // products: this lane's 8 rows a and 2 columns b of the tile
+    // one-wave tiles (TT = 32): the epilogue addressing is loaded first so
+    // that its latency overlaps the products (these kernels are held to
+    // their resident count by LDS, not registers).  This lane's 8 rows a
+    // and 2 columns b of the tile:
     const int32_t *__restrict__ RS = rseg + L.Roff;
     const int32_t *__restrict__ RO = maps + L.moff;
     const int32_t *__restrict__ CO = RO + (size_t)nseg * m;
     const int64_t *__restrict__ TG = stgt + L.task_begin;
     int rowa[2][4], colb[2], sa[2][4], sb[2];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        colb[bj] = tj * TT + wc * 32 + bj * 16 + li;
-        sb[bj] = RS[min(colb[bj], m - 1)];
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            rowa[bi][r] = ti * TT + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
-            sa[bi][r] = RS[min(rowa[bi][r], m - 1)];
-        }
     int ro[2][2][4], co[2][2][4];
     int64_t tg[2][2][4];
+    if constexpr (TT == 32) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+        for (int bj = 0; bj < 2; ++bj) {
+            colb[bj] = tj * TT + wc * 32 + bj * 16 + li;
+            sb[bj] = RS[min(colb[bj], m - 1)];
+        }
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                ro[bi][bj][r] = RO[(size_t)sb[bj] * m + min(rowa[bi][r], m - 1)];
-                co[bi][bj][r] = CO[(size_t)sa[bi][r] * m + min(colb[bj], m - 1)];
-                tg[bi][bj][r] = TG[sa[bi][r] * nseg + sb[bj]];
+                rowa[bi][r] = ti * TT + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
+                sa[bi][r] = RS[min(rowa[bi][r], m - 1)];
             }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ro[bi][bj][r] = RO[(size_t)sb[bj] * m + min(rowa[bi][r], m - 1)];
+                    co[bi][bj][r] = CO[(size_t)sa[bi][r] * m + min(colb[bj], m - 1)];
+                    tg[bi][bj][r] = TG[sa[bi][r] * nseg + sb[bj]];
+                }
+    }
 
     // operand staging: thread (row lr, inner kq) moves P / Qt entries
     // (row, k0 + kq + KS u), u < KU; rows past m read row m - 1 (never stored)
@@ -1120,27 +1124,66 @@ __global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restric
         __syncthreads();
     }
 
-    // subtract from the targets: all loads first, then the stores
     const acc4 acc[2][2] = {{c00, c01}, {c10, c11}};
-    int64_t off[2][2][4];
-    double tv[2][2][4];
+    if constexpr (TT == 32) {
+        // subtract from the targets: all loads first, then the stores
+        int64_t off[2][2][4];
+        double tv[2][2][4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool ok = rowa[bi][r] < m && colb[bj] < m && ro[bi][bj][r] >= 0 && co[bi][bj][r] >= 0;
+                    off[bi][bj][r] = ok ? tg[bi][bj][r] + ro[bi][bj][r] + co[bi][bj][r] : -1;
+                    tv[bi][bj][r] = slab[ok ? off[bi][bj][r] : 0];
+                }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - (double)acc[bi][bj][r];
+    } else {
+        // subtract from the targets, one 16-row half (bi) at a time so that
+        // few registers are live: the half's offsets (segment of every row and
+        // column, then the offset tables) and target values are loaded first,
+        // then its stores.  This lane's rows a and columns b of the tile:
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            colb[bj] = tj * TT + wc * 32 + bj * 16 + li;
+            sb[bj] = RS[min(colb[bj], m - 1)];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            int rh[4], sh[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const bool ok = rowa[bi][r] < m && colb[bj] < m && ro[bi][bj][r] >= 0 && co[bi][bj][r] >= 0;
-                off[bi][bj][r] = ok ? tg[bi][bj][r] + ro[bi][bj][r] + co[bi][bj][r] : -1;
-                tv[bi][bj][r] = slab[ok ? off[bi][bj][r] : 0];
+                rh[r] = ti * TT + wr * 32 + bi * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
+                sh[r] = RS[min(rh[r], m - 1)];
             }
+            int64_t off[2][4];
+            double tv[2][4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+            for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+                for (int r = 0; r < 4; ++r) {
+                    const int roh = RO[(size_t)sb[bj] * m + min(rh[r], m - 1)];
+                    const int coh = CO[(size_t)sh[r] * m + min(colb[bj], m - 1)];
+                    const int64_t tgh = TG[sh[r] * nseg + sb[bj]];
+                    const bool ok = rh[r] < m && colb[bj] < m && roh >= 0 && coh >= 0;
+                    off[bj][r] = ok ? tgh + roh + coh : -1;
+                    tv[bj][r] = slab[ok ? off[bj][r] : 0];
+                }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (off[bi][bj][r] >= 0) slab[off[bi][bj][r]] = tv[bi][bj][r] - (double)acc[bi][bj][r];
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (off[bj][r] >= 0) slab[off[bj][r]] = tv[bj][r] - (double)acc[bi][bj][r];
+        }
+    }
 }
 
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s) {

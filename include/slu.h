@@ -146,6 +146,12 @@ int slu_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowp
                       const int32_t *const *colidx, const int32_t *grid_dims,
                       const slu_options *opt, slu_handle **out);
 
+/* Host threads used by the parallel parts of slu_analyze and
+ * slu_analyze_batch (the Schur-update offset tables, level by level): 0
+ * (the default) takes the hardware's count, at most 16.  The analysis is the
+ * same for every count.  Process-wide; SLU_ERR_ARG for a negative count. */
+int slu_set_host_threads(int threads);
+
 /* Device bytes the handle needs (factor storage + structure + scratch). */
 int slu_workspace_size(const slu_handle *h, size_t *bytes);
 

@@ -3,8 +3,10 @@
 #include "analyze.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace slu {
 
@@ -192,6 +194,56 @@ void symbolic_fill(int64_t n, const std::vector<int64_t> &bp, const std::vector<
 
 inline int64_t align32(int64_t x) { return (x + 31) & ~(int64_t)31; }
 
+// Host threads for the parallel parts of the analysis (0: the hardware's
+// count, at most 16).
+std::atomic<int> g_host_threads{0};
+
+int host_threads() {
+    int t = g_host_threads.load();
+    if (t <= 0) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        t = hw == 0 ? 1 : (int)std::min(hw, 16u);
+    }
+    return t;
+}
+
+// f(i) for i in [0, count), chunks of `chunk` indices handed out in order to
+// the host threads; f must touch only data that no other index touches.
+template <class F>
+void parallel_for(int64_t count, int64_t chunk, F &&f) {
+    const int nt = (int)std::min<int64_t>(host_threads(), (count + chunk - 1) / chunk);
+    if (nt <= 1) {
+        for (int64_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int64_t b = next.fetch_add(chunk);
+            if (b >= count) break;
+            const int64_t e = std::min(count, b + chunk);
+            for (int64_t i = b; i < e; ++i) f(i);
+        }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread &th : pool) th.join();
+}
+
+// Positions of the increasing values v[0..nv) in the sorted array b[0..len)
+// (-1 where absent): a binary search for the first, then a forward walk
+// (the values of one segment are close together in b).
+void sorted_pos(const int32_t *b, int32_t len, const int32_t *v, int32_t nv, int32_t *out) {
+    if (nv <= 0) return;
+    int32_t p = (int32_t)(std::lower_bound(b, b + len, v[0]) - b);
+    for (int32_t a = 0; a < nv; ++a) {
+        while (p < len && b[p] < v[a]) ++p;
+        out[a] = (p < len && b[p] == v[a]) ? p : -1;
+    }
+}
+
 int32_t lower_pos(const int32_t *b, int32_t len, int32_t v) {
     const int32_t *it = std::lower_bound(b, b + len, v);
     if (it == b + len || *it != v) return -1;
@@ -199,6 +251,8 @@ int32_t lower_pos(const int32_t *b, int32_t len, int32_t v) {
 }
 
 }  // namespace
+
+void set_host_threads(int threads) { g_host_threads.store(threads < 0 ? 0 : threads); }
 
 int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_options &opt,
             Analysis *out, const std::vector<int64_t> *segments) {
@@ -240,12 +294,53 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         an.iperm[v] = (int32_t)k;
     }
 
-    // symbolic fill of the permuted symmetrised pattern
+    // symbolic fill of the permuted symmetrised pattern; stacked independent
+    // systems (no entry couples two of them) are filled on host threads, one
+    // system per task, and concatenated
     {
         std::vector<int64_t> bp;
         std::vector<int32_t> bi;
         permuted_symmetric(an, &bp, &bi);
-        symbolic_fill(n, bp, bi, &an.s_colptr, &an.s_rowidx);
+        bool split = segments && segments->size() > 2;
+        if (split) {
+            const std::vector<int64_t> &sg = *segments;
+            for (size_t q = 0; q + 1 < sg.size() && split; ++q)
+                for (int64_t k = sg[q]; k < sg[q + 1] && split; ++k)
+                    for (int64_t e = bp[k]; e < bp[k + 1]; ++e)
+                        if (bi[e] < sg[q] || bi[e] >= sg[q + 1]) {
+                            split = false;
+                            break;
+                        }
+        }
+        if (!split) {
+            symbolic_fill(n, bp, bi, &an.s_colptr, &an.s_rowidx);
+        } else {
+            const std::vector<int64_t> &sg = *segments;
+            const int64_t ns = (int64_t)sg.size() - 1;
+            std::vector<std::vector<int64_t>> cps(ns);
+            std::vector<std::vector<int32_t>> ris(ns);
+            parallel_for(ns, 1, [&](int64_t q) {
+                const int64_t s0 = sg[q], s1 = sg[q + 1], nq = s1 - s0;
+                std::vector<int64_t> lp(nq + 1);
+                std::vector<int32_t> li((size_t)(bp[s1] - bp[s0]));
+                for (int64_t k = 0; k <= nq; ++k) lp[k] = bp[s0 + k] - bp[s0];
+                for (int64_t e = bp[s0]; e < bp[s1]; ++e) li[e - bp[s0]] = (int32_t)(bi[e] - s0);
+                symbolic_fill(nq, lp, li, &cps[q], &ris[q]);
+            });
+            an.s_colptr.assign(n + 1, 0);
+            int64_t tot = 0;
+            for (int64_t q = 0; q < ns; ++q) tot += (int64_t)ris[q].size();
+            an.s_rowidx.resize((size_t)tot);
+            int64_t base = 0;
+            for (int64_t q = 0; q < ns; ++q) {
+                const int64_t s0 = sg[q], nq = sg[q + 1] - s0;
+                for (int64_t k = 0; k < nq; ++k) an.s_colptr[s0 + k + 1] = base + cps[q][k + 1];
+                for (size_t e = 0; e < ris[q].size(); ++e) an.s_rowidx[(size_t)base + e] = (int32_t)(ris[q][e] + s0);
+                base += (int64_t)ris[q].size();
+                std::vector<int64_t>().swap(cps[q]);
+                std::vector<int32_t>().swap(ris[q]);
+            }
+        }
     }
     const int64_t nnzL = an.s_colptr[n];
 
@@ -553,16 +648,32 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
     // where RO[sb] (m entries at maps[moff + sb * m]) and CO[sa] (m entries
     // at maps[moff + (nseg + sa) * m]) are the row / column offsets inside
     // the target, -1 where S has no entry there.
-    for (int64_t i = 0; i < p; ++i) {
-        LevelDev &L = an.levels[i];
-        L.task_begin = (int64_t)an.stgt.size();
-        L.moff = (int64_t)an.maps.size();
-        const int32_t *rows_i = an.R_idx.data() + L.Roff;
-        const int32_t nseg = L.seg_end - L.seg_begin;
-        if (L.kappa > 0) {
-            an.stored_flops += 2.0 * 2.0 * (double)L.m * L.kappa * L.kappa / 2.0;
-            an.stored_flops += 2.0 * (double)L.m * L.m * L.kappa;
-            an.maps.resize(an.maps.size() + 2 * (size_t)nseg * L.m, -1);
+    // The tables are sized in level order first; then the levels fill their
+    // disjoint parts on host threads (dynamic chunks of levels).
+    {
+        int64_t moff = 0, toff = 0;
+        for (int64_t i = 0; i < p; ++i) {
+            LevelDev &L = an.levels[i];
+            const int32_t nseg = L.seg_end - L.seg_begin;
+            L.task_begin = toff;
+            L.moff = moff;
+            if (L.kappa > 0) {
+                an.stored_flops += 2.0 * 2.0 * (double)L.m * L.kappa * L.kappa / 2.0;
+                an.stored_flops += 2.0 * (double)L.m * L.m * L.kappa;
+                moff += 2 * (int64_t)nseg * L.m;
+                toff += (int64_t)nseg * nseg;
+            }
+            L.task_end = toff;
+        }
+        if (toff >= ((int64_t)1 << 31) || moff >= ((int64_t)1 << 40)) return SLU_ERR_LIMIT;
+        an.maps.assign((size_t)moff, -1);
+        an.stgt.assign((size_t)toff, 0);
+        std::atomic<int> too_big{0};
+        parallel_for(p, 16, [&](int64_t i) {
+            const LevelDev &L = an.levels[i];
+            if (L.kappa <= 0) return;
+            const int32_t *rows_i = an.R_idx.data() + L.Roff;
+            const int32_t nseg = L.seg_end - L.seg_begin;
             int32_t *RO = an.maps.data() + L.moff;
             int32_t *CO = RO + (size_t)nseg * L.m;
             for (int32_t sa = 0; sa < nseg; ++sa) {
@@ -586,10 +697,13 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                         // L block (k, j) inside P_j: row = position in rows_j, column = position in K_j
                         tgt = Lj.offP;
                         const int32_t *rows_j = an.R_idx.data() + Lj.Roff;
-                        for (int32_t a = 0; a < A.len; ++a) ro[a] = lower_pos(rows_j, Lj.m, rows_i[A.start + a]);
+                        sorted_pos(rows_j, Lj.m, rows_i + A.start, A.len, ro);
                         for (int32_t c = 0; c < B.len; ++c) {
                             const int64_t t = an.posK[rows_i[B.start + c]];
-                            if (t >= 0 && t * Lj.m >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
+                            if (t >= 0 && t * Lj.m >= ((int64_t)1 << 31)) {
+                                too_big.store(1);
+                                return;
+                            }
                             co[c] = t < 0 ? -1 : (int32_t)(t * Lj.m);
                         }
                     } else {
@@ -598,19 +712,20 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                         const int32_t *rows_k = an.R_idx.data() + Lk.Roff;
                         for (int32_t a = 0; a < A.len; ++a) {
                             const int64_t t = an.posK[rows_i[A.start + a]];
-                            if (t >= 0 && t * Lk.m >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
+                            if (t >= 0 && t * Lk.m >= ((int64_t)1 << 31)) {
+                                too_big.store(1);
+                                return;
+                            }
                             ro[a] = t < 0 ? -1 : (int32_t)(t * Lk.m);
                         }
-                        for (int32_t c = 0; c < B.len; ++c) co[c] = lower_pos(rows_k, Lk.m, rows_i[B.start + c]);
+                        sorted_pos(rows_k, Lk.m, rows_i + B.start, B.len, co);
                     }
-                    an.stgt.push_back(tgt);
+                    an.stgt[(size_t)L.task_begin + (size_t)sa * nseg + sb] = tgt;
                 }
             }
-        }
-        L.task_end = (int64_t)an.stgt.size();
+        });
+        if (too_big.load()) return SLU_ERR_LIMIT;
     }
-    if ((int64_t)an.stgt.size() >= ((int64_t)1 << 31) || an.maps.size() >= ((size_t)1 << 40))
-        return SLU_ERR_LIMIT;
 
     // schedule: waves of levels with equal height in the dependency tree of
     // the blocks.  Level i waits for every level j < i whose panels couple to

@@ -162,6 +162,9 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
 // Geometric nested dissection of an nx x ny x nz grid (new -> old).
 void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *perm);
 
+// Host threads of the analysis' parallel parts (0: hardware count, at most 16).
+void set_host_threads(int threads);
+
 // Algorithm 3 with the exact-integer readings of the sampling.
 void irregular_blocking(const std::vector<int64_t> &blockptr, int sample_points, int step,
                         int max_num, int advance, std::vector<int64_t> *ptr);

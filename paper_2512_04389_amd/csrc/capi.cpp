@@ -705,6 +705,12 @@ const char *slu_error_string(int code) {
     }
 }
 
+int slu_set_host_threads(int threads) {
+    if (threads < 0) return SLU_ERR_ARG;
+    slu::set_host_threads(threads);
+    return SLU_OK;
+}
+
 int slu_last_hip_error(void) { return t_last_hip; }
 
 const char *slu_hip_error_string(int hip_code) { return hipGetErrorString((hipError_t)hip_code); }

@@ -171,3 +171,26 @@ def test_batch_analysis_errors():
     bad[0] = n
     with pytest.raises(slu.SluError):
         slu.SparseLU.batch([(n, rp, ci), (n, rp, bad)])
+
+
+def test_analysis_independent_of_host_threads():
+    # the parallel parts of the analysis (per-system symbolic fill, the
+    # Schur-update offset tables) give the same plan on one thread or many
+    import paper_2512_04389_amd as slu
+    from paper_2512_04389_amd import _abi
+    sys_ = [synth.batch_system(s) for s in (1, 2, 129, 140, 200)]
+    systems = [(x[0], x[1], x[2]) for x in sys_]
+    dims = [x[4] for x in sys_]
+    plans = []
+    try:
+        for threads in (1, 4):
+            assert _abi.lib.slu_set_host_threads(threads) == _abi.SLU_OK
+            h = slu.SparseLU.batch(systems, ordering="grid_nd", grid_dims=dims)
+            cp, ri = h.pattern()
+            plans.append((h.info(), h.workspace_size(), h.blocking(), cp, ri))
+    finally:
+        _abi.lib.slu_set_host_threads(0)
+    (i1, w1, b1, c1, r1), (i4, w4, b4, c4, r4) = plans
+    assert i1 == i4 and w1 == w4
+    assert np.array_equal(b1, b4) and np.array_equal(c1, c4) and np.array_equal(r1, r4)
+    assert _abi.lib.slu_set_host_threads(-1) == _abi.SLU_ERR_ARG

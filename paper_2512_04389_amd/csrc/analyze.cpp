@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <new>
 #include <numeric>
 #include <thread>
 
@@ -208,7 +209,9 @@ int host_threads() {
 }
 
 // f(i) for i in [0, count), chunks of `chunk` indices handed out in order to
-// the host threads; f must touch only data that no other index touches.
+// the host threads; f must touch only data that no other index touches.  An
+// allocation failure in any thread is rethrown (std::bad_alloc) in the
+// caller's thread once every thread has stopped.
 template <class F>
 void parallel_for(int64_t count, int64_t chunk, F &&f) {
     const int nt = (int)std::min<int64_t>(host_threads(), (count + chunk - 1) / chunk);
@@ -217,12 +220,17 @@ void parallel_for(int64_t count, int64_t chunk, F &&f) {
         return;
     }
     std::atomic<int64_t> next{0};
+    std::atomic<int> failed{0};
     auto work = [&]() {
-        for (;;) {
-            const int64_t b = next.fetch_add(chunk);
-            if (b >= count) break;
-            const int64_t e = std::min(count, b + chunk);
-            for (int64_t i = b; i < e; ++i) f(i);
+        try {
+            for (;;) {
+                const int64_t b = next.fetch_add(chunk);
+                if (b >= count || failed.load()) break;
+                const int64_t e = std::min(count, b + chunk);
+                for (int64_t i = b; i < e; ++i) f(i);
+            }
+        } catch (const std::bad_alloc &) {
+            failed.store(1);
         }
     };
     std::vector<std::thread> pool;
@@ -230,6 +238,7 @@ void parallel_for(int64_t count, int64_t chunk, F &&f) {
     for (int t = 1; t < nt; ++t) pool.emplace_back(work);
     work();
     for (std::thread &th : pool) th.join();
+    if (failed.load()) throw std::bad_alloc();
 }
 
 // Positions of the increasing values v[0..nv) in the sorted array b[0..len)

@@ -140,7 +140,9 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 //   1. wave 0 factors the w x w diagonal of the chunk in registers;
 //   2. the coupled rows (L = A U_cc^{-1}) and coupled columns
 //      (U = L_cc^{-1} A) are solved by substitution, one per lane;
-//   3. the four waves update the R x R trailing entries with FP64 MFMA.
+//   3. the four waves update the R x R trailing entries with FP64 MFMA;
+//   4. the solved panel of steps 1-2 (kept in LDS) is written to D at the
+//      start of step 3.
 // Pivots are inverted by a reciprocal refined with two Newton steps; a zero
 // or non-finite pivot records its permuted column in info[0].
 // One column chunk of the chunked GETRF.  W = 16 is the full-width chunk
@@ -286,7 +288,8 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     // 2. coupled rows (x U_cc = a) and coupled columns (L_cc y = a): one
     // per lane, forward substitution over the chunk's w columns with the
     // factor entries broadcast from LDS.  Rows take items [0, nr64),
-    // columns [nr64, nr64 + nr), so no wave mixes the two kinds.
+    // columns [nr64, nr64 + nr), so no wave mixes the two kinds.  The
+    // results stay in LDS; they go to D in step 4.
     const int nr64 = (nr + 63) & ~63;
     for (int it = tid; it < nr64 + nr; it += 256) {
         double x[16];
@@ -304,14 +307,9 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                             if (j2 < w) x[j2] -= xj * Pn[j2 * T + j];          // U(j, j2)
                     }
                 }
-                const size_t row = (size_t)Rs[it];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    if (j < w) {
-                        Pn[j * T + w + it] = x[j];
-                        D[row + (size_t)(c0 + j) * b] = x[j];
-                    }
-                }
+                for (int j = 0; j < 16; ++j)
+                    if (j < w) Pn[j * T + w + it] = x[j];
             }
         } else {
             const int sI = it - nr64;
@@ -325,21 +323,33 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                         if (j2 < w) x[j2] -= Pn[j * T + j2] * x[j];            // L(j2, j)
                 }
             }
-            double *__restrict__ col = D + c0 + (size_t)Rs[sI] * b;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (j < w) {
-                    Uc[sI * wu + j] = x[j];
-                    col[j] = x[j];
-                }
-            }
+            for (int j = 0; j < 16; ++j)
+                if (j < w) Uc[sI * wu + j] = x[j];
         }
     }
     __syncthreads();
+    // 4. the solved panel goes from LDS to D, once the first round of
+    // trailing tiles (loaded in steps 0/1, long since arrived) has been
+    // waited for: no later step of the block reads these entries, and
+    // stores issued any earlier would sit ahead of that wait in the in-order
+    // memory counter.  Consecutive threads write consecutive coupled rows of
+    // a column, and 16-entry runs of a coupled column.
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    for (int e = tid; e < nr * w; e += 256) {
+        const int j = e / nr, it = e - j * nr;
+        D[(size_t)Rs[it] + (size_t)(c0 + j) * b] = Pn[j * T + w + it];
+    }
+    for (int e = tid; e < nr * w; e += 256) {
+        const int sI = e / w, j = e - sI * w;
+        D[c0 + j + (size_t)Rs[sI] * b] = Uc[sI * wu + j];
+    }
     // trailing update of the coupled rows x coupled columns: the rank-w
-    // product on MFMA applied to each wave's loaded tiles, stored back
-    for (int q0 = wave; q0 < ntiles; q0 += 32) {
-        if (q0 != wave) load_tiles(q0);
+    // product on MFMA applied to each wave's loaded tiles, stored back.  The
+    // first round (tiles loaded in steps 0/1) is peeled off the loop of later
+    // rounds, which load their own tiles, so its MFMAs need no wait beyond
+    // the one above.
+    auto tile_round = [&](int q0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int q = q0 + 4 * u;
@@ -381,6 +391,11 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
                 }
             }
         }
+    };
+    tile_round(wave);
+    for (int q0 = wave + 32; q0 < ntiles; q0 += 32) {
+        load_tiles(q0);
+        tile_round(q0);
     }
     __syncthreads();
 }

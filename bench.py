@@ -7,8 +7,8 @@ value scatter plus the whole level loop of GETRF / GESSM / TSTRF / SSSSM.
 The analysis (ordering, symbolic fill, blocking) runs once before timing and
 is reported separately, as is the solve with its backward error.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build measures one
-GPU only.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the library has no
+multi-GPU path, so only one GPU is measured.
 """
 from __future__ import annotations
 
@@ -243,7 +243,7 @@ def main():
         pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], TRAFFIC_FILE)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
+        print("bench.py measures one GPU only: the library has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -209,6 +209,15 @@ def batch_bench(args):
     B = torch.from_numpy(np.concatenate([synth.csr_matvec(x[0], x[1], x[2], x[3], xs[o:o + x[0]])
                                          for x, o in zip(sy, np.cumsum([0] + [x[0] for x in sy[:-1]]))])).cuda()
     X = h.solve(B)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    X = h.solve(B)
+    e1.record(st)
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1)
     eta = float(h.backward_error(vals, B, X)[0])
     h.set_precision("fp32")
     ms32, _ = time_factor(h, vals, args.steps, args.warmup, torch)
@@ -219,7 +228,7 @@ def batch_bench(args):
                                           "n_total": h.n, "nnz_s": info["nnz_s"], "flops": F,
                                           "levels": info["nblocks"], "waves": info["waves"],
                                           "rounds": info["rounds"]},
-            "analyze_s": analyze_s, "ms_launches": ms, "ms_graph": ms_g, "eta": eta,
+            "analyze_s": analyze_s, "ms_launches": ms, "ms_graph": ms_g, "solve_ms": solve_ms, "eta": eta,
             "fp32": {"ms_graph": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "corrections": its,
                      "eta": float(np.max(eta_r)), "converged": bool(conv)}}
     print(json.dumps(line), flush=True)

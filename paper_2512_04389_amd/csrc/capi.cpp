@@ -128,28 +128,34 @@ int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t 
         hipError_t e = slu::launch_gather_perm(d, B + c0 * ld, ld, nc, s);
         if (hip_failed(e)) return SLU_ERR_HIP;
         // forward sweep wave by wave: the diagonal solves of a wave's levels
-        // together, then each level's update of later rows (in level order,
-        // so the sums are deterministic); the backward sweep mirrors it
+        // together, then their updates of later rows one Schur-update round
+        // at a time (a round's levels have disjoint target rows, and every
+        // row takes its updates in round order, so the sums are
+        // deterministic); the backward sweep mirrors it, with the updates of
+        // a whole wave together (each level writes only its own block)
         for (const slu::WaveInfo &w : an.waves) {
             const int nlev = w.end - w.begin;
             if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
                 return SLU_ERR_HIP;
-            for (int q = w.begin; q < w.end; ++q) {
-                const slu::LevelDev &L = an.levels[an.wave_levels[q]];
-                if (L.m > 0 && L.kappa > 0 &&
-                    hip_failed(slu::launch_fwd_update(d, an.wave_levels[q], L.m, nc, trans, s)))
+            for (int r = w.round_begin; r < w.round_end; ++r) {
+                const slu::RoundInfo &ri = an.rounds[r];
+                int max_m = 0;
+                for (int q = ri.begin; q < ri.end; ++q) max_m = std::max(max_m, an.levels[an.round_levels[q]].m);
+                if (hip_failed(slu::launch_fwd_update(d, d.round_levels + ri.begin, ri.end - ri.begin, max_m, nc,
+                                                      trans, s)))
                     return SLU_ERR_HIP;
             }
         }
         for (size_t wi = an.waves.size(); wi-- > 0;) {
             const slu::WaveInfo &w = an.waves[wi];
+            const int nlev = w.end - w.begin;
+            int max_kappa = 0;
             for (int q = w.begin; q < w.end; ++q) {
                 const slu::LevelDev &L = an.levels[an.wave_levels[q]];
-                if (L.m > 0 && L.kappa > 0 &&
-                    hip_failed(slu::launch_bwd_update(d, an.wave_levels[q], L.kappa, nc, trans, s)))
-                    return SLU_ERR_HIP;
+                if (L.m > 0) max_kappa = std::max(max_kappa, L.kappa);
             }
-            const int nlev = w.end - w.begin;
+            if (hip_failed(slu::launch_bwd_update(d, d.wave_levels + w.begin, nlev, max_kappa, nc, trans, s)))
+                return SLU_ERR_HIP;
             if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
                 return SLU_ERR_HIP;
         }

@@ -1483,97 +1483,110 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
 }
 
 // W[rows_i[a]] -= X[a, :] . W[r0 + K_i]   (X = P_i, or Qt_i when transposed)
-// A workgroup takes 64 rows (one per lane); its four waves split the inner
-// index, whose W values are staged in LDS 256 at a time; the four partial
-// sums are added in LDS in a fixed order.
+// for the levels of one Schur-update round, whose target rows are disjoint:
+// blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) its 64-row
+// tiles.  A workgroup takes 64 rows (one per lane); its four waves split the
+// inner index, whose W values are staged in LDS 256 at a time; the four
+// partial sums are added in LDS in a fixed order.
 constexpr int kUpdSlice = 256;
 
 __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ slab,
-                                                    const LevelDev *__restrict__ levels, int level,
+                                                    const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl,
                                                     const int32_t *__restrict__ Kidx,
                                                     const int32_t *__restrict__ Ridx, double *__restrict__ W,
                                                     int64_t n, int nc, int trans) {
     __shared__ double xk[kUpdSlice * kSolveCols];
     __shared__ double part[4][kSolveCols][64];
-    const LevelDev L = levels[level];
+    const LevelDev L = levels[lvl[blockIdx.x]];
     const int m = L.m, kap = L.kappa;
     const double *__restrict__ X = slab + (trans ? L.offQ : L.offP);
     const int32_t *__restrict__ K = Kidx + L.Koff;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int a = blockIdx.x * 64 + lane;
-    const int ac = min(a, m - 1);
-    double acc[kSolveCols];
+    for (int tile = blockIdx.y; tile * 64 < m; tile += gridDim.y) {
+        const int a = tile * 64 + lane;
+        const int ac = min(a, m - 1);
+        double acc[kSolveCols];
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
-    for (int t0 = 0; t0 < kap; t0 += kUpdSlice) {
-        const int nt = min(kUpdSlice, kap - t0);
-        __syncthreads();
-        for (int e = tid; e < nt * nc; e += 256) {
-            const int t = e / nc, c = e - t * nc;
-            xk[e] = W[L.r0 + K[t0 + t] + (size_t)c * n];
-        }
-        __syncthreads();
-        // this wave's inner indices t = wave + 4 u, eight loads in flight
-        for (int u0 = wave; u0 < nt; u0 += 32) {
-            double pv[8];
+        for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
+        for (int t0 = 0; t0 < kap; t0 += kUpdSlice) {
+            const int nt = min(kUpdSlice, kap - t0);
+            __syncthreads();
+            for (int e = tid; e < nt * nc; e += 256) {
+                const int t = e / nc, c = e - t * nc;
+                xk[e] = W[L.r0 + K[t0 + t] + (size_t)c * n];
+            }
+            __syncthreads();
+            // this wave's inner indices t = wave + 4 u, eight loads in flight
+            for (int u0 = wave; u0 < nt; u0 += 32) {
+                double pv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) pv[q] = X[ac + (size_t)(t0 + min(u0 + 4 * q, nt - 1)) * m];
+                for (int q = 0; q < 8; ++q) pv[q] = X[ac + (size_t)(t0 + min(u0 + 4 * q, nt - 1)) * m];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int t = u0 + 4 * q;
-                if (t < nt) {
+                for (int q = 0; q < 8; ++q) {
+                    const int t = u0 + 4 * q;
+                    if (t < nt) {
 #pragma unroll
-                    for (int c = 0; c < kSolveCols; ++c)
-                        if (c < nc) acc[c] += pv[q] * xk[t * nc + c];
+                        for (int c = 0; c < kSolveCols; ++c)
+                            if (c < nc) acc[c] += pv[q] * xk[t * nc + c];
+                    }
                 }
             }
         }
-    }
+        __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c)
-        if (c < nc) part[wave][c][lane] = acc[c];
-    __syncthreads();
-    for (int e = tid; e < 64 * nc; e += 256) {
-        const int c = e >> 6, r = e & 63;
-        const int row = blockIdx.x * 64 + r;
-        if (row < m) {
-            const double v = (part[0][c][r] + part[1][c][r]) + (part[2][c][r] + part[3][c][r]);
-            W[Ridx[L.Roff + row] + (size_t)c * n] -= v;
+        for (int c = 0; c < kSolveCols; ++c)
+            if (c < nc) part[wave][c][lane] = acc[c];
+        __syncthreads();
+        for (int e = tid; e < 64 * nc; e += 256) {
+            const int c = e >> 6, r = e & 63;
+            const int row = tile * 64 + r;
+            if (row < m) {
+                const double v = (part[0][c][r] + part[1][c][r]) + (part[2][c][r] + part[3][c][r]);
+                W[Ridx[L.Roff + row] + (size_t)c * n] -= v;
+            }
         }
     }
 }
 
 // W[r0 + K_i[t]] -= sum_a X[a, t] W[rows_i[a]]   (X = Qt_i, or P_i when transposed)
+// for the levels of one wave (each writes only its own block's rows):
+// blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) the column
+// t, blockIdx.z the right-hand side; one wave reduces over a.
 __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                   int level, const int32_t *__restrict__ Kidx,
+                                                   const int32_t *__restrict__ lvl,
+                                                   const int32_t *__restrict__ Kidx,
                                                    const int32_t *__restrict__ Ridx, double *__restrict__ W,
                                                    int64_t n, int trans) {
-    const LevelDev L = levels[level];
+    const LevelDev L = levels[lvl[blockIdx.x]];
     const int m = L.m;
-    const int t = blockIdx.x, c = blockIdx.y;
-    const double *__restrict__ X = slab + (trans ? L.offP : L.offQ) + (size_t)t * m;
+    if (m == 0) return;
+    const int c = blockIdx.z;
     const int32_t *__restrict__ R = Ridx + L.Roff;
     const double *__restrict__ Wc = W + (size_t)c * n;
-    double acc = 0.0;
-    for (int a = threadIdx.x; a < m; a += 64) acc += X[a] * Wc[R[a]];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (threadIdx.x == 0) W[L.r0 + Kidx[L.Koff + t] + (size_t)c * n] -= acc;
+    for (int t = blockIdx.y; t < L.kappa; t += gridDim.y) {
+        const double *__restrict__ X = slab + (trans ? L.offP : L.offQ) + (size_t)t * m;
+        double acc = 0.0;
+        for (int a = threadIdx.x; a < m; a += 64) acc += X[a] * Wc[R[a]];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (threadIdx.x == 0) W[L.r0 + Kidx[L.Koff + t] + (size_t)c * n] -= acc;
+    }
 }
 
-
-
-hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s) {
-    if (m <= 0) return hipSuccess;
-    const int64_t blocks = ((int64_t)m + 63) / 64;
-    hipLaunchKernelGGL(k_fwd_update, dim3((unsigned)blocks), dim3(256), 0, s, d.slab, d.levels, level, d.K_idx,
-                       d.R_idx, d.scratch, d.n, nc, trans);
+hipError_t launch_fwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int nc, int trans,
+                             hipStream_t s) {
+    if (nlev <= 0 || max_m <= 0) return hipSuccess;
+    const int64_t tiles = ((int64_t)max_m + 63) / 64;
+    hipLaunchKernelGGL(k_fwd_update, dim3((unsigned)nlev, (unsigned)std::min<int64_t>(tiles, 65535)), dim3(256), 0,
+                       s, d.slab, d.levels, lvl, d.K_idx, d.R_idx, d.scratch, d.n, nc, trans);
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_update(const DevPlan &d, int level, int kappa, int nc, int trans, hipStream_t s) {
-    if (kappa <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bwd_update, dim3((unsigned)kappa, (unsigned)nc), dim3(64), 0, s, d.slab, d.levels, level,
-                       d.K_idx, d.R_idx, d.scratch, d.n, trans);
+hipError_t launch_bwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_kappa, int nc, int trans,
+                             hipStream_t s) {
+    if (nlev <= 0 || max_kappa <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bwd_update, dim3((unsigned)nlev, (unsigned)std::min(max_kappa, 4096), (unsigned)nc),
+                       dim3(64), 0, s, d.slab, d.levels, lvl, d.K_idx, d.R_idx, d.scratch, d.n, trans);
     return hipGetLastError();
 }
 

@@ -72,8 +72,14 @@ hipError_t launch_scatter_perm(const DevPlan &d, double *X, int64_t ld, int nc, 
 size_t solve_diag_lds_bytes(int max_b, int nc);
 hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
                                   int trans, hipStream_t s);
-hipError_t launch_fwd_update(const DevPlan &d, int level, int m, int nc, int trans, hipStream_t s);
-hipError_t launch_bwd_update(const DevPlan &d, int level, int kappa, int nc, int trans, hipStream_t s);
+// Forward updates of the nlev levels in lvl (levels whose target rows are
+// disjoint: one Schur-update round); max_m is their largest m.
+hipError_t launch_fwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int nc, int trans,
+                             hipStream_t s);
+// Backward updates of the nlev levels in lvl (one wave: each writes only its
+// own block's rows); max_kappa is their largest kappa.
+hipError_t launch_bwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_kappa, int nc, int trans,
+                             hipStream_t s);
 
 // Backward-error pieces: norms[0..nc) = ||r||, [16..) = ||x||, [32..) = ||b||, [48] = ||op(A)||.
 hipError_t launch_residual_norms(const DevPlan &d, const double *values, const double *B,

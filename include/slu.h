@@ -203,6 +203,19 @@ int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t 
  * launch-by-launch path.  enable = 0 releases the graph. */
 int slu_set_graph(slu_handle *h, int enable);
 
+/* GETRF launch shape (Algorithm 1, the factorization of the diagonal
+ * blocks).  A wave whose chunked diagonal blocks (more than 128 rows) include
+ * one with trailing work of at least min_work, counted as the sum over its
+ * column chunks of (coupled rows)^2, is factored chunk by chunk in two
+ * launches per chunk: the panel of every block by one workgroup each, then
+ * the trailing update spread over the GPU one 16 x 16 tile per workgroup.
+ * Other waves take one launch with one workgroup per block.  Both give the
+ * same factors bit for bit; the split pays on large dense diagonal blocks.
+ * Default 8e6; 0 splits every wave with a chunked block.  A captured graph
+ * (slu_set_graph) is released and recaptured.  SLU_ERR_ARG for a negative
+ * or NaN min_work. */
+int slu_set_getrf_split(slu_handle *h, double min_work);
+
 /* Factorization precision.  SLU_PRECISION_FP64: every step in FP64.
  * SLU_PRECISION_FP32: the Schur updates (Algorithm 1's SSSSM, nearly all of
  * the flops) take their operands rounded to FP32 and accumulate in FP32 on

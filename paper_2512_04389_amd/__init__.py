@@ -185,6 +185,12 @@ class SparseLU:
         it in later factors (see ``slu_set_graph``)."""
         check(lib.slu_set_graph(self._h, 1 if enable else 0), "slu_set_graph")
 
+    def set_getrf_split(self, min_work):
+        """Trailing work from which a wave's GETRF is split into a panel and
+        a chip-wide trailing-update launch per column chunk (see
+        ``slu_set_getrf_split``; 0 splits every wave with a chunked block)."""
+        check(lib.slu_set_getrf_split(self._h, float(min_work)), "slu_set_getrf_split")
+
     def set_precision(self, precision):
         """``"fp64"`` (default) or ``"fp32"`` (Schur updates in FP32 on the
         matrix cores, see ``slu_set_precision``) for later factorizations."""

@@ -36,6 +36,9 @@ struct slu_handle {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
     int graph_precision = -1;
+    // waves whose chunked diagonal blocks reach this trailing work (sum over
+    // a block's chunks of nr^2) take the split GETRF
+    double getrf_split_work = 8e6;
 };
 
 namespace {
@@ -428,7 +431,37 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     for (const slu::WaveInfo &w : an.waves) {
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
-        SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
+        // split GETRF when one of the wave's chunked blocks has enough
+        // trailing work to be worth spreading over the chip
+        bool split = false;
+        int nsteps = 1;
+        if (nlev <= 65535) {
+            for (int q = w.begin; q < w.end; ++q) {
+                const slu::LevelDev &L = an.levels[an.wave_levels[q]];
+                if (L.b <= slu::kLdsDenseMax) continue;
+                double work = 0.0;
+                for (int c = L.chunk_begin; c < L.chunk_end; ++c)
+                    work += (double)an.chunks[c].nr * an.chunks[c].nr;
+                if (work >= h->getrf_split_work) split = true;
+                nsteps = std::max(nsteps, L.chunk_end - L.chunk_begin);
+            }
+        }
+        if (!split) {
+            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
+        } else {
+            for (int k = 0; k < nsteps; ++k) {
+                SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_step(d, lv, nlev, k, w.lds_getrf, s));
+                int max_tiles = 0;
+                for (int q = w.begin; q < w.end; ++q) {
+                    const slu::LevelDev &L = an.levels[an.wave_levels[q]];
+                    if (L.b <= slu::kLdsDenseMax || L.chunk_begin + k >= L.chunk_end) continue;
+                    const int ntl = (an.chunks[L.chunk_begin + k].nr + 15) / 16;
+                    max_tiles = std::max(max_tiles, ntl * ntl);
+                }
+                if (max_tiles > 0)
+                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_trail(d, lv, nlev, k, max_tiles, s));
+            }
+        }
         if (w.max_m > 0 && w.max_kp > 0) {
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
@@ -519,6 +552,16 @@ int slu_set_graph(slu_handle *h, int enable) {
     if (!h) return SLU_ERR_ARG;
     h->use_graph = enable != 0;
     if (!h->use_graph && h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    return SLU_OK;
+}
+
+int slu_set_getrf_split(slu_handle *h, double min_work) {
+    if (!h || !(min_work >= 0.0)) return SLU_ERR_ARG;
+    h->getrf_split_work = min_work;
+    if (h->gexec) {   // a captured graph holds the other launch sequence
         (void)hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;
     }

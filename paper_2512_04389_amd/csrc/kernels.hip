@@ -149,7 +149,7 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 // (every width guard folds away); W = 0 takes the width at run time (the
 // last chunk of a block).  Loads guarded per lane read a clamped, valid
 // address and select zero, so they are issued without branches.
-template <int W>
+template <int W, bool TRAIL = true>
 __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, int r0, const ChunkDev &C,
                                                  const int *Rs, const double *Rd, double *work,
                                                  unsigned long long *__restrict__ info, int wave, int lane,
@@ -230,7 +230,7 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
             for (int s = 0; s < 4; ++s) a[s] = (4 * gg + s < w && gi < w) ? a[s] : 0.0;
             lu16_2d(a, w, lane, bad, myrd);
         };
-        if (nr > 0) {
+        if (TRAIL && nr > 0) {
             __builtin_amdgcn_sched_barrier(0);
             load_tiles(0);
             __builtin_amdgcn_sched_barrier(0);
@@ -282,7 +282,7 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
             store_item(it, v);
             if (it2 < 2 * nr) store_item(it2, v2);
         }
-        if (nr > 0) load_tiles(wave);
+        if (TRAIL && nr > 0) load_tiles(wave);
     }
     __syncthreads();
     // 2. coupled rows (x U_cc = a) and coupled columns (L_cc y = a): one
@@ -335,7 +335,7 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
     // stores issued any earlier would sit ahead of that wait in the in-order
     // memory counter.  Consecutive threads write consecutive coupled rows of
     // a column, and 16-entry runs of a coupled column.
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    if (TRAIL) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     for (int e = tid; e < nr * w; e += 256) {
         const int j = e / nr, it = e - j * nr;
         D[(size_t)Rs[it] + (size_t)(c0 + j) * b] = Pn[j * T + w + it];
@@ -392,10 +392,12 @@ __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, 
             }
         }
     };
-    tile_round(wave);
-    for (int q0 = wave + 32; q0 < ntiles; q0 += 32) {
-        load_tiles(q0);
-        tile_round(q0);
+    if (TRAIL) {
+        tile_round(wave);
+        for (int q0 = wave + 32; q0 < ntiles; q0 += 32) {
+            load_tiles(q0);
+            tile_round(q0);
+        }
     }
     __syncthreads();
 }
@@ -573,6 +575,111 @@ __global__ __launch_bounds__(256) void k_getrf_wave(double *__restrict__ slab, c
 hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_getrf_wave, dim3((unsigned)nlev), dim3(256), (size_t)lds_bytes, s, d.slab, d.levels, lvl,
                        d.chunks, d.chunk_rows, d.info);
+    return hipGetLastError();
+}
+
+// Split GETRF for waves whose chunked blocks are dense enough that one
+// workgroup's trailing updates dominate: step k of every level of the wave
+// runs in two launches.  k_getrf_step: one workgroup per level factors the
+// diagonal of chunk k, solves its coupled rows and columns and writes them to
+// D (a level with b <= 128 is factored whole at k = 0; a level without a
+// chunk k does nothing).  k_getrf_trail: one wave per 16 x 16 trailing tile
+// of chunk k, numbered per level, applies the rank-w update with FP64 MFMA,
+// reading the solved panel from D.  Arithmetic per entry as in the one-launch
+// chunked GETRF.
+__global__ __launch_bounds__(256) void k_getrf_step(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl, int k,
+                                                    const ChunkDev *__restrict__ chunks,
+                                                    const int32_t *__restrict__ crows,
+                                                    unsigned long long *__restrict__ info) {
+    extern __shared__ double lds[];
+    const LevelDev L = levels[lvl[blockIdx.x]];
+    if (L.b <= 128) {
+        if (k == 0) getrf_dense(slab, L, lds, info);
+        return;
+    }
+    const int ch = L.chunk_begin + k;
+    if (ch >= L.chunk_end) return;
+    double *__restrict__ D = slab + L.offD;
+    const int b = L.b;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int maxnr = L.pad;
+    int *Rs = (int *)lds;
+    double *Rd = lds + ((2 * maxnr + 1) >> 1);
+    double *work = Rd + 16;
+    const ChunkDev C = chunks[ch];
+    for (int q = tid; q < C.nr; q += 256) Rs[q] = crows[C.roff + q];
+    __syncthreads();
+    if (C.w == 16)
+        getrf_chunk_step<16, false>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
+    else
+        getrf_chunk_step<0, false>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
+}
+
+__global__ __launch_bounds__(64) void k_getrf_trail(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                    const int32_t *__restrict__ lvl, int k,
+                                                    const ChunkDev *__restrict__ chunks,
+                                                    const int32_t *__restrict__ crows) {
+    const LevelDev L = levels[lvl[blockIdx.y]];
+    if (L.b <= 128) return;
+    const int ch = L.chunk_begin + k;
+    if (ch >= L.chunk_end) return;
+    const ChunkDev C = chunks[ch];
+    const int nr = C.nr, w = C.w, c0 = C.c0, b = L.b;
+    const int ntl = (nr + 15) >> 4;
+    const int q = blockIdx.x;
+    if (q >= ntl * ntl) return;
+    double *__restrict__ D = slab + L.offD;
+    const int32_t *__restrict__ Rs = crows + C.roff;
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int ti = q / ntl, tj = q - ti * ntl;
+    // output element (coupled column 16 tj + lk + 4 r, coupled row 16 ti + li)
+    const int ar = 16 * ti + li, sc = 16 * tj + li;
+    const bool va = ar < nr, vcc = sc < nr;
+    const size_t rowo = (size_t)Rs[va ? ar : nr - 1];
+    const size_t colo = (size_t)Rs[vcc ? sc : nr - 1] * b;
+    int cs[4];
+    double4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sc2 = 16 * tj + lk + 4 * r;
+        cs[r] = Rs[sc2 < nr ? sc2 : nr - 1];
+        acc[r] = D[rowo + (size_t)cs[r] * b];
+    }
+    double al[4], bl[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int kx = 4 * kk + lk;
+        const int kc = kx < w ? kx : 0;
+        al[kk] = D[c0 + kc + colo];                      // U(c0 + k, Rs[sc])
+        bl[kk] = D[rowo + (size_t)(c0 + kc) * b];        // L(Rs[ar], c0 + k)
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int kx = 4 * kk + lk;
+        if (4 * kk < w) {
+            const double a = (kx < w && vcc) ? -al[kk] : 0.0;
+            const double bv = (kx < w && va) ? bl[kk] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sc2 = 16 * tj + lk + 4 * r;
+        if (va && sc2 < nr) D[rowo + (size_t)cs[r] * b] = acc[r];
+    }
+}
+
+hipError_t launch_getrf_step(const DevPlan &d, const int32_t *lvl, int nlev, int k, int lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_getrf_step, dim3((unsigned)nlev), dim3(256), (size_t)lds_bytes, s, d.slab, d.levels, lvl, k,
+                       d.chunks, d.chunk_rows, d.info);
+    return hipGetLastError();
+}
+
+hipError_t launch_getrf_trail(const DevPlan &d, const int32_t *lvl, int nlev, int k, int max_tiles, hipStream_t s) {
+    if (max_tiles <= 0 || nlev <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_getrf_trail, dim3((unsigned)max_tiles, (unsigned)nlev), dim3(64), 0, s, d.slab, d.levels,
+                       lvl, k, d.chunks, d.chunk_rows);
     return hipGetLastError();
 }
 
@@ -1716,6 +1823,8 @@ hipError_t setup_kernel_attributes() {
                             160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_getrf_wave, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_getrf_step, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_panel_solve<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);

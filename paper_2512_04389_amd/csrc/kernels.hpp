@@ -58,6 +58,10 @@ hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_scatter(const DevPlan &d, const double *values, hipStream_t s);
 hipError_t launch_info_reset(const DevPlan &d, hipStream_t s);
 hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int lds_bytes, hipStream_t s);
+// Split GETRF of a wave, step k: the chunk-k panel of every level, then the
+// chunk-k trailing tiles (max_tiles: the most over the wave's levels).
+hipError_t launch_getrf_step(const DevPlan &d, const int32_t *lvl, int nlev, int k, int lds_bytes, hipStream_t s);
+hipError_t launch_getrf_trail(const DevPlan &d, const int32_t *lvl, int nlev, int k, int max_tiles, hipStream_t s);
 // soff: first workgroup of each of the wave's levels; slots: their total.
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const int32_t *soff, int nlev, int slots,
                                   hipStream_t s);

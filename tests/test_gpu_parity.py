@@ -127,6 +127,47 @@ def test_zero_pivot_and_nonfinite():
     assert h.info()["factored"] == 1
 
 
+@pytest.mark.parametrize("case", ["convdiff-14-regular-200", "convdiff-14-regular-700", "band-600x4-regular-1200",
+                                  "bbd-2400-regular-300"])
+def test_split_getrf_matches_one_launch(case):
+    # slu_set_getrf_split(0): every wave with a chunked block (b > 128) takes
+    # the panel + chip-wide trailing-tile launches per chunk; the factors
+    # must equal the one-launch GETRF's bit for bit (also under graph replay),
+    # and the oracle's within the parity tolerance
+    import paper_2512_04389_amd as slu
+    if case.startswith("convdiff"):
+        n, rp, ci, v = synth.convection_diffusion_3d(14)
+        opts = dict(ordering="grid_nd", grid_dims=(14, 14, 14), blocking="regular",
+                    block_size=int(case.rsplit("-", 1)[1]))
+    elif case.startswith("band"):
+        n, rp, ci, v = synth.grid_laplacian((600, 4, 1))
+        opts = dict(blocking="regular", block_size=1200)
+    else:
+        n, rp, ci, v = synth.bbd_circuit(n=2400, nblocks=8, border=80, border_nnz=2000, seed=4)
+        opts = dict(blocking="regular", block_size=300)
+    announce("split GETRF " + case)
+    h = slu.SparseLU(n, rp, ci, **opts).bind()
+    assert max(np.diff(h.blocking())) > 128
+    vals = torch.from_numpy(v).cuda()
+    h.factor(vals)
+    l0, u0 = h.factors()
+    h.set_getrf_split(0)
+    h.factor(vals)
+    l1, u1 = h.factors()
+    np.testing.assert_array_equal(l1, l0)
+    np.testing.assert_array_equal(u1, u0)
+    h.set_graph(True)
+    for _ in range(2):
+        h.factor(vals)
+        l2, u2 = h.factors()
+        np.testing.assert_array_equal(l2, l0)
+        np.testing.assert_array_equal(u2, u0)
+    h.set_graph(False)
+    check_factors(h, n, rp, ci, v, opts)
+    with pytest.raises(slu.SluError):
+        h.set_getrf_split(-1.0)
+
+
 def test_determinism_and_refactor():
     import paper_2512_04389_amd as slu
     n, rp, ci, v = synth.laplacian_3d(12)

@@ -66,10 +66,12 @@ def time_factor(h, vals, steps, warmup, torch):
 
 
 KERNEL_SOURCES = ("paper_2512_04389_amd/csrc/kernels.hip", "paper_2512_04389_amd/csrc/kernels.hpp",
-                  "paper_2512_04389_amd/csrc/analyze.cpp", "paper_2512_04389_amd/csrc/analyze.hpp")
+                  "paper_2512_04389_amd/csrc/analyze.cpp", "paper_2512_04389_amd/csrc/analyze.hpp",
+                  "paper_2512_04389_amd/csrc/capi.cpp")   # capi.cpp: the launch sequence
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_getrf_wave_lap3d48.json")
 TRAFFIC_WORKLOAD = "lap3d48"   # the workload the stored counters were taken on
-KERNEL_SYMBOL = {"getrf": ("k_getrf_wave",), "panel": ("k_tri_gather", "k_panel_solve"), "ssssm": ("k_ssssm",)}
+KERNEL_SYMBOL = {"getrf": ("k_getrf_wave", "k_getrf_step", "k_getrf_trail"),
+                 "panel": ("k_tri_gather", "k_panel_solve"), "ssssm": ("k_ssssm",)}
 COPY_BYTES = 256 << 20
 
 

@@ -211,7 +211,7 @@ int slu_set_graph(slu_handle *h, int enable);
  * the trailing update spread over the GPU one 16 x 16 tile per workgroup.
  * Other waves take one launch with one workgroup per block.  Both give the
  * same factors bit for bit; the split pays on large dense diagonal blocks.
- * Default 8e6; 0 splits every wave with a chunked block.  A captured graph
+ * Default 2e5; 0 splits every wave with a chunked block.  A captured graph
  * (slu_set_graph) is released and recaptured.  SLU_ERR_ARG for a negative
  * or NaN min_work. */
 int slu_set_getrf_split(slu_handle *h, double min_work);

@@ -38,7 +38,7 @@ struct slu_handle {
     int graph_precision = -1;
     // waves whose chunked diagonal blocks reach this trailing work (sum over
     // a block's chunks of nr^2) take the split GETRF
-    double getrf_split_work = 8e6;
+    double getrf_split_work = 2e5;
 };
 
 namespace {

@@ -146,8 +146,9 @@ hipError_t launch_info_reset(const DevPlan &d, hipStream_t s) {
 // Pivots are inverted by a reciprocal refined with two Newton steps; a zero
 // or non-finite pivot records its permuted column in info[0].
 // One column chunk of the chunked GETRF.  W = 16 is the full-width chunk
-// (every width guard folds away); W = 0 takes the width at run time (the
-// last chunk of a block).  Loads guarded per lane read a clamped, valid
+// (every width guard folds away), W = 8 the width that large dense blocks
+// take under the LDS budget; W = 0 takes the width at run time (the last
+// chunk of a block, narrower budgets).  Loads guarded per lane read a clamped, valid
 // address and select zero, so they are issued without branches.
 template <int W, bool TRAIL = true>
 __device__ __forceinline__ void getrf_chunk_step(double *__restrict__ D, int b, int r0, const ChunkDev &C,
@@ -431,6 +432,8 @@ __device__ __attribute__((always_inline)) void getrf_chunked(double *__restrict_
         }
         if (C.w == 16)
             getrf_chunk_step<16>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
+        else if (C.w == 8)
+            getrf_chunk_step<8>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
         else
             getrf_chunk_step<0>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
     }
@@ -612,6 +615,8 @@ __global__ __launch_bounds__(256) void k_getrf_step(double *__restrict__ slab, c
     __syncthreads();
     if (C.w == 16)
         getrf_chunk_step<16, false>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
+    else if (C.w == 8)
+        getrf_chunk_step<8, false>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
     else
         getrf_chunk_step<0, false>(D, b, L.r0, C, Rs, Rd, work, info, wave, lane, tid);
 }

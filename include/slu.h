@@ -166,12 +166,20 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
  * stream.  Returns SLU_OK or SLU_ZERO_PIVOT. */
 int slu_factor(slu_handle *h, const double *values, void *stream);
 
-/* Solve A X = B.  B, X: device float64, column-major n x nrhs with leading
- * dimension ld >= n; X may alias B.  Requires a successful factor. */
+/* Solve A X = B (the system Ax = b that the factorization serves, Section 1):
+ * X = perm^T U^{-1} L^{-1} perm B by a forward sweep with L and a backward
+ * sweep with U over the same blocks and waves as the factorization.
+ * B, X: device float64, column-major n x nrhs with leading dimension
+ * ld >= n; X may alias B; both stay the caller's.  Requires a successful
+ * factor (SLU_ERR_NOT_FACTORED otherwise); SLU_ERR_ARG for a null pointer
+ * with nrhs > 0, nrhs < 0 or ld < n.  Stream-ordered, no host wait. */
 int slu_solve(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld,
               void *stream);
 
-/* Solve A^T X = B with the same factors (U^T then L^T sweeps). */
+/* Solve A^T X = B with the same factors (Section 1's Ax = b for the
+ * transposed matrix, A^T = perm^T U^T L^T perm): a forward sweep with U^T,
+ * then a backward sweep with L^T.  Arguments, ownership and errors as in
+ * slu_solve. */
 int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs,
                         int64_t ld, void *stream);
 

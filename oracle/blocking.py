@@ -7,8 +7,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   submatrix.  It counts, per column, the entries below the diagonal at the
   row where they sit; then blockptr[i+1] = blockptr[i] + 2*num[i] + 1 (the
   row's lower entries, their mirror images and the diagonal).
-* ``irregular_blocking`` -- the 1000-point sampling of the percentage curve
-  and Algorithm 3 (Section 4.3).
+* ``irregular_blocking`` -- the 1000-point sampling of the feature curve
+  (blockptr over its last entry) and Algorithm 3 (Section 4.3).
 * ``regular_blocking`` -- fixed-size 2D blocking (Section 3.2).
 
 Readings where the text is incomplete (each is listed in the design notes):
@@ -20,8 +20,9 @@ R2  the loop runs while i + step <= Sp (the printed bound would read past the
     the loop did not end on it;
 R3  Sp = min(1000, N) intervals; sample s sits at row pos(s) = floor(s*N/Sp),
     s = 0..Sp, so samples are distinct rows even for N < 1000;
-R4  the threshold is step/Sp (the printed "sample_pointers" is a typo) and the
-    comparison is "greater or equal", evaluated exactly in integers:
+R4  the threshold is step over the number of sample intervals (the printed
+    name of that count is garbled) and the comparison is "greater or equal",
+    evaluated exactly in integers:
         (blockptr[pos(i+step)] - blockptr[pos(i)]) * Sp >= step * blockptr[N]
     which is pct[i+step] - pct[i] >= step/Sp multiplied through by
     Sp*blockptr[N] > 0;
@@ -50,12 +51,6 @@ def diag_block_ptr(n, colptr, rowidx):
     return blockptr
 
 
-def percentage(blockptr):
-    """The nonzero percentage curve (Section 4.2): blockptr / blockptr[N]."""
-    bp = np.asarray(blockptr, dtype=np.float64)
-    return bp / bp[-1] if bp[-1] else bp
-
-
 def sample_rows(N, sample_points=1000):
     """Rows of the Sp+1 uniform samples (reading R3)."""
     sp = min(int(sample_points), int(N))
@@ -64,28 +59,34 @@ def sample_rows(N, sample_points=1000):
 
 
 def irregular_blocking(blockptr, sample_points=1000, step=2, max_num=3, advance=1):
-    """Algorithm 3 on the sampled percentage curve; returns ptr (int64)."""
+    """Structure-aware blocking (Section 4.3, Algorithm 3); returns ptr (int64).
+
+    The feature curve is read at the Sp + 1 sample rows.  Every window of
+    ``step`` sample intervals, its start moving by ``advance`` samples, is
+    tested once, in order: it is dense when its increment of the curve is at
+    least step/Sp of the total.  The window's end row becomes a boundary when
+    the window is dense, or when the ``max_num`` windows before it passed
+    without a boundary; N closes the last block.
+    """
     blockptr = np.asarray(blockptr, dtype=np.int64)
     N = blockptr.shape[0] - 1
     if N == 0:
         return np.zeros(1, dtype=np.int64)
-    pos, sp = sample_rows(N, sample_points)
+    rows, sp = sample_rows(N, sample_points)
     total = int(blockptr[N])
+    starts = np.arange(0, sp - step + 1, advance, dtype=np.int64)
+    ends = rows[starts + step]
+    increment = blockptr[ends] - blockptr[rows[starts]]
+    # increment / total >= step / Sp, multiplied through by Sp * total > 0
+    dense = increment * sp >= step * total
     ptr = [0]
-    l = 0
-    i = 0
-    while i + step <= sp:
-        lo = int(blockptr[pos[i]])
-        hi = int(blockptr[pos[i + step]])
-        if (hi - lo) * sp >= step * total:      # dense region
-            ptr.append(int(pos[i + step]))
-            l = 0
-        elif l >= max_num:                       # avoid too large blocks
-            ptr.append(int(pos[i + step]))
-            l = 0
+    passed = 0
+    for end, is_dense in zip(ends.tolist(), dense.tolist()):
+        if is_dense or passed >= max_num:
+            ptr.append(end)
+            passed = 0
         else:
-            l += 1
-        i += advance
+            passed += 1
     if ptr[-1] != N:
         ptr.append(N)
     return np.asarray(ptr, dtype=np.int64)

@@ -24,25 +24,8 @@ def flops(colptr, kmax=None):
 
 
 def residual(n, rowptr, colidx, values, X, B):
-    """R = B - A X (fp64), X and B of shape (n,) or (n, k)."""
-    X = np.asarray(X, dtype=np.float64)
-    B = np.asarray(B, dtype=np.float64)
-    vec = X.ndim == 1
-    Xm = X[:, None] if vec else X
-    Bm = B[:, None] if vec else B
-    R = np.array(Bm, dtype=np.float64, copy=True)
-    rp = np.asarray(rowptr, dtype=np.int64)
-    ci = np.asarray(colidx, dtype=np.int64)
-    v = np.asarray(values, dtype=np.float64)
-    for i in range(n):
-        lo, hi = rp[i], rp[i + 1]
-        if hi > lo:
-            R[i, :] -= v[lo:hi] @ Xm[ci[lo:hi], :]
-    return R[:, 0] if vec else R
-
-
-def residual_fast(n, rowptr, colidx, values, X, B):
-    """Same as ``residual`` using a vectorised row reduction (large n)."""
+    """R = B - A X in fp64 (X and B of shape (n,) or (n, k)), one row
+    reduction per row of A."""
     X = np.asarray(X, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     vec = X.ndim == 1
@@ -88,7 +71,7 @@ def backward_error(n, rowptr, colidx, values, X, B, transpose=False):
         np.add.at(tptr, ci + 1, 1)
         tptr = np.cumsum(tptr)
         rp, ci, v = tptr, rows[order], v[order]
-    R = residual_fast(n, rp, ci, v, Xm, Bm)
+    R = residual(n, rp, ci, v, Xm, Bm)
     na = norm_inf_matrix(n, rp, v)
     nx = np.abs(Xm).max(axis=0) if n else np.zeros(Xm.shape[1])
     nb = np.abs(Bm).max(axis=0) if n else np.zeros(Bm.shape[1])

@@ -31,6 +31,27 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_dev(name, t, device, numel=None, rows=None):
+    """Raise ValueError unless t is a float64 tensor on the bound device
+    (contiguous when numel is given: it is passed as a flat array; with rows,
+    a vector of that length or a matrix of that many rows)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64:
+        raise ValueError("%s must be float64, got %s" % (name, t.dtype))
+    if not t.is_cuda or (device is not None and t.device != device):
+        raise ValueError("%s must live on %s, got %s" % (name, device, t.device))
+    if numel is not None:
+        if t.numel() != numel or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous tensor of %d entries, got shape %s"
+                             % (name, numel, tuple(t.shape)))
+    if rows is not None:
+        if t.dim() not in (1, 2) or t.shape[0] != rows:
+            raise ValueError("%s must have %d rows (a vector or an n x nrhs matrix), got shape %s"
+                             % (name, rows, tuple(t.shape)))
+
+
 class SparseLU:
     """One analyzed pattern: ``slu_analyze`` at construction, then
     ``bind`` (workspace), ``factor``, ``solve`` / ``solve_transpose``."""
@@ -66,6 +87,7 @@ class SparseLU:
                               ctypes.byref(h)), "slu_analyze")
         self._h = h
         self._ws = None
+        self.device = None
         self._serial = 0          # bumped by every successful factor
 
     @classmethod
@@ -104,6 +126,7 @@ class SparseLU:
         self._perm_in = None
         self._h = h
         self._ws = None
+        self.device = None
         self._serial = 0
         self.sizes = nvec
         return self
@@ -147,12 +170,24 @@ class SparseLU:
         nbytes = self.workspace_size()
         if workspace is None:
             workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 device tensor")
         check(lib.slu_bind_workspace(self._h, _dptr(workspace), workspace.numel(), _stream(stream)),
               "slu_bind_workspace")
         self._ws = workspace
+        self.device = workspace.device
         return self
 
+    def _nnz(self):
+        return int(self.info()["nnz_a"])
+
+    def _bound(self):
+        if self._ws is None:
+            raise RuntimeError("bind() a workspace first")
+        return self.device
+
     def factor(self, values, stream=None):
+        _check_dev("values", values, self._bound(), numel=self._nnz())
         self._serial += 1
         rc = lib.slu_factor(self._h, _dptr(values), _stream(stream))
         if rc == _abi.SLU_ZERO_PIVOT:
@@ -161,6 +196,12 @@ class SparseLU:
 
     def _solve(self, fn, B, X, stream):
         import torch
+        dev = self._bound()
+        _check_dev("B", B, dev, rows=self.n)
+        if X is not None:
+            _check_dev("X", X, dev, rows=self.n)
+            if X.shape != B.shape:
+                raise ValueError("X must have the shape of B %s, got %s" % (tuple(B.shape), tuple(X.shape)))
         vec = B.dim() == 1
         Bm = B.reshape(-1, 1) if vec else B
         nrhs = Bm.shape[1]
@@ -201,6 +242,9 @@ class SparseLU:
         """FP64 iterative refinement on the current factors; returns
         (X, corrections applied, per-column backward errors, converged)."""
         import torch
+        dev = self._bound()
+        _check_dev("values", values, dev, numel=self._nnz())
+        _check_dev("B", B, dev, rows=self.n)
         vec = B.dim() == 1
         Bc = (B.reshape(-1, 1) if vec else B).t().contiguous()
         Xc = torch.empty_like(Bc)
@@ -218,6 +262,11 @@ class SparseLU:
         """-G X^T restricted to A's pattern, in the CSR order of the
         analysis (see ``slu_value_gradient``)."""
         import torch
+        dev = self._bound()
+        _check_dev("G", G, dev, rows=self.n)
+        _check_dev("X", X, dev, rows=self.n)
+        if G.shape != X.shape:
+            raise ValueError("G and X must have one shape, got %s and %s" % (tuple(G.shape), tuple(X.shape)))
         Gc = (G.reshape(-1, 1) if G.dim() == 1 else G).t().contiguous()
         Xc = (X.reshape(-1, 1) if X.dim() == 1 else X).t().contiguous()
         nnz = int(self._rowptr[-1])
@@ -227,6 +276,12 @@ class SparseLU:
         return out
 
     def backward_error(self, values, B, X, transpose=False, stream=None):
+        dev = self._bound()
+        _check_dev("values", values, dev, numel=self._nnz())
+        _check_dev("B", B, dev, rows=self.n)
+        _check_dev("X", X, dev, rows=self.n)
+        if B.shape != X.shape:
+            raise ValueError("B and X must have one shape, got %s and %s" % (tuple(B.shape), tuple(X.shape)))
         vec = B.dim() == 1
         Bc = (B.reshape(-1, 1) if vec else B).t().contiguous()
         Xc = (X.reshape(-1, 1) if vec else X).t().contiguous()

@@ -62,11 +62,15 @@ void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *per
 }
 
 // ------------------------------------------------------------ Algorithm 3
-// Readings: Sp = min(sample_points, N) intervals, sample s at row
-// floor(s*N/Sp); the loop runs while i + step <= Sp advancing by `advance`;
-// the threshold step/Sp is compared exactly as
-// (blockptr[pos(i+step)] - blockptr[pos(i)]) * Sp >= step * blockptr[N];
-// N closes the last block.
+// Structure-aware blocking (Section 4.3).  The feature curve blockptr is read
+// at Sp + 1 rows, Sp = min(sample_points, N), sample s at floor(s N / Sp).
+// Windows of `step` sample intervals are tested in order, the start moving by
+// `advance` samples.  A window's end becomes a block boundary when the window
+// holds at least step/Sp of all entries of S (a dense stretch: fine blocks),
+// or when max_num windows have passed since the last boundary (a sparse
+// stretch: blocks of a bounded number of windows).  The threshold test is
+// exact in integers, increment * Sp >= step * blockptr[N]; N closes the
+// last block.
 void irregular_blocking(const std::vector<int64_t> &blockptr, int sample_points, int step,
                         int max_num, int advance, std::vector<int64_t> *ptr) {
     ptr->clear();
@@ -74,20 +78,17 @@ void irregular_blocking(const std::vector<int64_t> &blockptr, int sample_points,
     ptr->push_back(0);
     if (N <= 0) return;
     const int64_t sp = std::min<int64_t>(sample_points, N);
-    auto pos = [&](int64_t s) { return (int64_t)(((__int128)s * N) / sp); };
-    const __int128 total = blockptr[N];
-    int64_t l = 0;
-    for (int64_t i = 0; i + step <= sp; i += advance) {
-        const int64_t lo = blockptr[pos(i)];
-        const int64_t hi = blockptr[pos(i + step)];
-        if ((__int128)(hi - lo) * sp >= (__int128)step * total) {  // dense region
-            ptr->push_back(pos(i + step));
-            l = 0;
-        } else if (l >= max_num) {                                 // block would grow too large
-            ptr->push_back(pos(i + step));
-            l = 0;
+    auto row = [&](int64_t s) { return (int64_t)(((__int128)s * N) / sp); };
+    const __int128 need = (__int128)step * blockptr[N];
+    int64_t passed = 0;   // windows since the last boundary
+    for (int64_t s = 0; s + step <= sp; s += advance) {
+        const int64_t end = row(s + step);
+        const bool dense = (__int128)(blockptr[end] - blockptr[row(s)]) * sp >= need;
+        if (dense || passed >= max_num) {
+            ptr->push_back(end);
+            passed = 0;
         } else {
-            ++l;
+            ++passed;
         }
     }
     if (ptr->back() != N) ptr->push_back(N);

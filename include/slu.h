@@ -224,6 +224,18 @@ int slu_set_graph(slu_handle *h, int enable);
  * or NaN min_work. */
 int slu_set_getrf_split(slu_handle *h, double min_work);
 
+/* Tiled GETRF (Algorithm 1's factorization of the diagonal blocks, with the
+ * GESSM / TSTRF / SSSSM steps inside the block applied tile by tile): a wave
+ * whose largest diagonal block has at least min_rows rows factors its blocks
+ * densely in 16 x 16 tiles, one launch per tile step spread over the GPU one
+ * tile per workgroup: the panel tiles are solved by products with the
+ * inverted diagonal tile of the previous step and every trailing tile is
+ * updated with FP64 MFMA; the diagonal tile of the step is then factored and
+ * inverted.  min_rows = 0 (the default) keeps the chunked GETRF on every
+ * wave.  Same factors as the other GETRF paths up to rounding.  A captured
+ * graph is released and recaptured.  SLU_ERR_ARG for a negative min_rows. */
+int slu_set_getrf_tiled(slu_handle *h, int min_rows);
+
 /* Factorization precision.  SLU_PRECISION_FP64: every step in FP64.
  * SLU_PRECISION_FP32: the Schur updates (Algorithm 1's SSSSM, nearly all of
  * the flops) take their operands rounded to FP32 and accumulate in FP32 on

@@ -232,6 +232,11 @@ class SparseLU:
         ``slu_set_getrf_split``; 0 splits every wave with a chunked block)."""
         check(lib.slu_set_getrf_split(self._h, float(min_work)), "slu_set_getrf_split")
 
+    def set_getrf_tiled(self, min_rows):
+        """Waves whose largest diagonal block has at least ``min_rows`` rows
+        take the tiled GETRF (see ``slu_set_getrf_tiled``; 0: none)."""
+        check(lib.slu_set_getrf_tiled(self._h, int(min_rows)), "slu_set_getrf_tiled")
+
     def set_precision(self, precision):
         """``"fp64"`` (default) or ``"fp32"`` (Schur updates in FP32 on the
         matrix cores, see ``slu_set_precision``) for later factorizations."""

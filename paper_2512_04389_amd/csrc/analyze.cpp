@@ -651,6 +651,18 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         an.tri_doubles = toff;
     }
 
+    // tiled GETRF work region (levels of more than one 16-row tile)
+    {
+        int64_t woff = 0;
+        for (int64_t i = 0; i < p; ++i) {
+            LevelDev &L = an.levels[i];
+            const int64_t need = tgetrf_level_doubles(L.b);
+            L.offW = need > 0 ? woff : -1;
+            woff += align32(need);
+        }
+        an.tgetrf_doubles = woff;
+    }
+
     // SSSSM: every pair (sa, sb) of segments of level i is a target
     // block (k, j) (sa-major order in stgt).  Product element (a, b), with a
     // in segment sa and b in segment sb, lands at

@@ -33,6 +33,7 @@ namespace slu {
 struct LevelDev {
     int64_t offD, offP, offQ;   // slab offsets in doubles
     int64_t offT;               // tri region offset in doubles
+    int64_t offW;               // tiled GETRF work region offset in doubles (-1: none)
     int64_t Koff, Roff;         // offsets into K_idx / R_idx
     int64_t task_begin, task_end;   // segment pairs (SSSSM targets) in stgt, sa-major
     int64_t moff;                   // SSSSM offset tables in maps
@@ -126,6 +127,7 @@ struct Analysis {
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
     std::vector<int32_t> trow_idx;
     int64_t tri_doubles = 0;
+    int64_t tgetrf_doubles = 0;      // tiled GETRF work region (panel copies, tile inverses)
     std::vector<int64_t> slot;       // A entry (CSR order) -> slab position
     std::vector<int32_t> posK;       // global column -> position in K of its block, or -1
 
@@ -151,6 +153,10 @@ constexpr int kSolveCont = 1 << 8;   // solve chunk continuing the previous one'
 constexpr int kLdsDenseMax = 128;
 // LDS budget of the chunked GETRF (bytes).
 constexpr int kGetrfLdsBudget = 150 * 1024;
+// Tiled GETRF: per level with b > 16 rows, two panel copies of 32 b doubles
+// (a tile column and a tile row of the diagonal block) and two pairs of
+// inverted 16 x 16 diagonal tiles.
+inline int64_t tgetrf_level_doubles(int32_t b) { return b > 16 ? 64 * (int64_t)b + 1024 : 0; }
 
 // Returns SLU_OK or an SLU_ERR_* code; fills *out.
 // segments (optional): ascending row offsets 0 = s_0 < s_1 < ... < s_k = n of

@@ -16,7 +16,7 @@ struct slu_handle {
     void *ws = nullptr;
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
-    size_t o_slab, o_tri, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
+    size_t o_slab, o_tri, o_tgetrf, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
         o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_rlev, o_rtile, o_tsoff, o_info, o_scratch, o_ir, o_norms, o_vals;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
@@ -39,6 +39,9 @@ struct slu_handle {
     // waves whose chunked diagonal blocks reach this trailing work (sum over
     // a block's chunks of nr^2) take the split GETRF
     double getrf_split_work = 2e5;
+    // waves whose largest diagonal block has at least this many rows take
+    // the tiled GETRF (0: none)
+    int getrf_tiled_rows = 0;
 };
 
 namespace {
@@ -64,6 +67,7 @@ void plan_workspace(slu_handle *h) {
     };
     h->o_slab = take((size_t)an.slab_doubles * 8);
     h->o_tri = take((size_t)an.tri_doubles * 8);
+    h->o_tgetrf = take((size_t)an.tgetrf_doubles * 8);
     h->o_trow_ptr = take(an.trow_ptr.size() * 4);
     h->o_trow_idx = take(an.trow_idx.size() * 4);
     h->o_levels = take(an.levels.size() * sizeof(slu::LevelDev));
@@ -330,6 +334,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     slu::DevPlan &d = h->dev;
     d.slab = (double *)(base + h->o_slab);
     d.tri = (double *)(base + h->o_tri);
+    d.tgetrf = an.tgetrf_doubles > 0 ? (double *)(base + h->o_tgetrf) : nullptr;
     d.trow_ptr = (const int32_t *)(base + h->o_trow_ptr);
     d.trow_idx = (const int32_t *)(base + h->o_trow_idx);
     d.levels = (const slu::LevelDev *)(base + h->o_levels);
@@ -431,6 +436,13 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     for (const slu::WaveInfo &w : an.waves) {
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
+        if (h->getrf_tiled_rows > 0 && w.max_b >= h->getrf_tiled_rows && nlev <= 65535) {
+            const int max_nt = (w.max_b + 15) / 16;
+            for (int k = 0; k < max_nt; ++k)
+                SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
+            goto getrf_done;
+        }
+        {
         // split GETRF when one of the wave's chunked blocks has enough
         // trailing work to be worth spreading over the chip
         bool split = false;
@@ -462,6 +474,8 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
                     SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_trail(d, lv, nlev, k, max_tiles, s));
             }
         }
+        }
+    getrf_done:
         if (w.max_m > 0 && w.max_kp > 0) {
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
@@ -561,6 +575,16 @@ int slu_set_graph(slu_handle *h, int enable) {
 int slu_set_getrf_split(slu_handle *h, double min_work) {
     if (!h || !(min_work >= 0.0)) return SLU_ERR_ARG;
     h->getrf_split_work = min_work;
+    if (h->gexec) {   // a captured graph holds the other launch sequence
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    return SLU_OK;
+}
+
+int slu_set_getrf_tiled(slu_handle *h, int min_rows) {
+    if (!h || min_rows < 0) return SLU_ERR_ARG;
+    h->getrf_tiled_rows = min_rows;
     if (h->gexec) {   // a captured graph holds the other launch sequence
         (void)hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;

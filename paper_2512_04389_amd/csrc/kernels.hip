@@ -688,6 +688,200 @@ hipError_t launch_getrf_trail(const DevPlan &d, const int32_t *lvl, int nlev, in
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ tiled GETRF
+// Pivot K of the no-pivot LU of a 16 x 16 tile in the 2D layout of lu16_2d
+// (lane i + 16 g holds a[s] = A(i, 4 g + s)), which also builds the inverses
+// of both factors: e (same layout, starts as I) takes the row operations of
+// the elimination and ends as L^{-1}; f (starts as I) takes the column
+// operations that clear U's rows right of the diagonal, col_j -= U(K, j) /
+// U(K, K) col_K, which turn I into the inverse of U's unit-diagonal form;
+// column K of f is final after pivot K and is divided by U(K, K) there, so f
+// ends as U^{-1}.  bad: the first zero or non-finite pivot (16 if none).
+template <int K>
+__device__ __forceinline__ void lu16inv_step(double (&a)[4], double (&e)[4], double (&f)[4], int i, int g,
+                                             int &bad) {
+    constexpr int g0 = K >> 2, s0 = K & 3;
+    const double piv = bcast_lane(a[s0], K + 16 * g0);
+    if (!(piv != 0.0 && isfinite(piv))) bad = min(bad, K);
+    const double rp = recip(piv);
+    const double lg = a[s0] * rp;
+    if (g == g0 && i > K) a[s0] = lg;
+    const double l = perm_lane(lg, i + 16 * g0);       // L(i, K) for i > K
+    const double fk = perm_lane(f[s0], i + 16 * g0);   // f(i, K)
+    double u[4], ek[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        u[s] = bcast16<K>(a[s]);                       // U(K, 4 g + s)
+        ek[s] = bcast16<K>(e[s]);                      // row K of L^{-1} (final)
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int j = 4 * g + s;
+        const double na = a[s] - l * u[s];
+        a[s] = (i > K && j > K) ? na : a[s];
+        const double ne = e[s] - l * ek[s];
+        e[s] = i > K ? ne : e[s];
+        const double nf = f[s] - (u[s] * rp) * fk;
+        f[s] = j > K ? nf : f[s];
+    }
+    if (g == g0) f[s0] *= rp;
+    if constexpr (K + 1 < 16) lu16inv_step<K + 1>(a, e, f, i, g, bad);
+}
+
+// Right-looking LU of dense diagonal blocks in 16 x 16 tiles, one launch per
+// tile step s for every level of a wave (grid.y), one wave per tile.  Launch
+// s >= 1 takes the panel p = s - 1 and updates every trailing tile (I, J),
+// I, J >= s:
+//     Lt = A(I, p) U_pp^{-1},   Ut = L_pp^{-1} A(p, J),   A(I, J) -= Lt Ut
+// (three 16 x 16 x 16 FP64 MFMA products); the inverted diagonal tiles come
+// from the previous launch.  Tiles (I, s) write Lt as the final L(I, p),
+// tiles (s, J) write Ut as U(p, J); the updated tiles of tile column and row
+// s are the next panel and go to a panel copy (two copies, by step parity),
+// so no launch reads a tile of D that it writes.  Tile (s, s) then factors
+// itself (lu16inv_step) and writes its L and U into D and their inverses for
+// the next launch.  Launch 0 factors tile (0, 0) and copies panel 0.  The
+// panel products are the substitutions of Algorithm 1's GESSM / TSTRF steps
+// inside the diagonal block, applied as products with the inverted triangles.
+// Entries outside S stay exactly zero: every term reaching one has a
+// structurally zero factor, and so do the inverses' entries they meet.
+__global__ __launch_bounds__(64) void k_getrf_tile(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                   const int32_t *__restrict__ lvl, int s,
+                                                   double *__restrict__ work,
+                                                   unsigned long long *__restrict__ info) {
+    __shared__ double tl[16 * 17];
+    const LevelDev L = levels[lvl[blockIdx.y]];
+    const int b = L.b;
+    const int nt = (b + 15) >> 4;
+    if (s >= nt) return;
+    const int q = blockIdx.x;
+    int I, J;
+    if (s == 0) {
+        if (q >= 2 * nt - 1) return;
+        I = q < nt ? q : 0;
+        J = q < nt ? 0 : q - nt + 1;
+    } else {
+        const int m = nt - s;
+        if (q >= m * m) return;
+        I = s + q / m;
+        J = s + q - (q / m) * m;
+    }
+    double *__restrict__ D = slab + L.offD;
+    double *__restrict__ W = work + (L.offW >= 0 ? L.offW : 0);
+    const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+    const int rI = 16 * I, cJ = 16 * J;
+    const bool rowok = rI + li < b, colok = cJ + li < b;
+    // tile (I, J) in the MFMA result layout: lane li + 16 g holds C(g + 4 r, li)
+    double4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = rI + g + 4 * r;
+        acc[r] = (colok && row < b) ? D[(size_t)(cJ + li) * b + row] : 0.0;
+    }
+    if (s >= 1) {
+        const int p = s - 1;
+        const double *__restrict__ Pc = W + (size_t)(p & 1) * 32 * b;   // tile column p, b x 16
+        const double *__restrict__ Pr = Pc + (size_t)16 * b;           // tile row p, 16 x b (column-major, ld 16)
+        const double *__restrict__ iL = W + 64 * (size_t)b + (p & 1) * 512;   // row-major
+        const double *__restrict__ iU = iL + 256;
+        double xa[4], ya[4], xb[4], yb[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + g;
+            xa[kk] = iU[k * 16 + li];                              // (iU^T)(li, k)
+            ya[kk] = rowok ? Pc[(size_t)k * b + rI + li] : 0.0;     // (A(I, p)^T)(k, li)
+            xb[kk] = iL[li * 16 + k];                              // iL(li, k)
+            yb[kk] = colok ? Pr[(size_t)(cJ + li) * 16 + k] : 0.0;  // A(p, J)(k, li)
+        }
+        // lt(r) = Lt^T(g + 4 r, li) = Lt(li, g + 4 r);  ut(r) = Ut(g + 4 r, li)
+        double4_t lt = {0.0, 0.0, 0.0, 0.0}, ut = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            lt = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk], ya[kk], lt, 0, 0, 0);
+            ut = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[kk], yb[kk], ut, 0, 0, 0);
+        }
+        // A(I, J) -= Lt Ut: Lt(li, 4 kk + g) and Ut(4 kk + g, li) are the
+        // operands of step kk exactly as the two products left them
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-lt[kk], ut[kk], acc, 0, 0, 0);
+        if (J == s && rowok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[(size_t)(16 * p + g + 4 * r) * b + rI + li] = lt[r];
+        }
+        if (I == s && colok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[(size_t)(cJ + li) * b + 16 * p + g + 4 * r] = ut[r];
+        }
+    }
+    if (I != s || J != s) {
+        if (J == s) {   // next panel, tile column: its copy only (launch s + 1 writes L there)
+            double *__restrict__ Pc = W + (size_t)(s & 1) * 32 * b;
+            if (colok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rI + g + 4 * r;
+                    if (row < b) Pc[(size_t)li * b + row] = acc[r];
+                }
+            }
+        } else if (I == s) {   // next panel, tile row
+            double *__restrict__ Pr = W + (size_t)(s & 1) * 32 * b + (size_t)16 * b;
+            if (colok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Pr[(size_t)(cJ + li) * 16 + g + 4 * r] = acc[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rI + g + 4 * r;
+                if (colok && row < b) D[(size_t)(cJ + li) * b + row] = acc[r];
+            }
+        }
+        return;
+    }
+    // tile (s, s): factor it.  Rows / columns past b are an identity, so the
+    // padding never yields a bad pivot.
+    const int w = min(16, b - rI);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = g + 4 * r;
+        double v = acc[r];
+        if (row >= w || li >= w) v = row == li ? 1.0 : 0.0;
+        tl[row * 17 + li] = v;
+    }
+    __syncthreads();
+    double a[4], e[4], f[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        a[t] = tl[li * 17 + 4 * g + t];
+        e[t] = li == 4 * g + t ? 1.0 : 0.0;
+        f[t] = e[t];
+    }
+    int bad = 16;
+    lu16inv_step<0>(a, e, f, li, g, bad);
+    if (bad < w && lane == 0) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int col = 4 * g + t;
+        if (li < w && col < w) D[(size_t)(rI + col) * b + rI + li] = a[t];
+    }
+    if (s + 1 < nt) {
+        double *__restrict__ iL = W + 64 * (size_t)b + (s & 1) * 512;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            iL[li * 16 + 4 * g + t] = e[t];
+            iL[256 + li * 16 + 4 * g + t] = f[t];
+        }
+    }
+}
+
+hipError_t launch_getrf_tile(const DevPlan &d, const int32_t *lvl, int nlev, int s, int max_nt, hipStream_t st) {
+    if (nlev <= 0 || s >= max_nt) return hipSuccess;
+    const int m = max_nt - s;
+    const unsigned gx = s == 0 ? (unsigned)(2 * max_nt - 1) : (unsigned)(m * m);
+    hipLaunchKernelGGL(k_getrf_tile, dim3(gx, (unsigned)nlev), dim3(64), 0, st, d.slab, d.levels, lvl, s, d.tgetrf,
+                       d.info);
+    return hipGetLastError();
+}
+
 // ------------------------------------------- compact coupled triangles
 // One workgroup per 16 x 16 tile that the panel solves read, numbered over
 // the wave's levels (soff: first workgroup of each level): per level the nt

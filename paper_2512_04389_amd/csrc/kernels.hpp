@@ -13,6 +13,7 @@ namespace slu {
 struct DevPlan {
     double *slab;
     double *tri;                // compact coupled triangles (see LevelDev)
+    double *tgetrf;             // tiled GETRF panel copies and inverted tiles (LevelDev.offW)
     const int32_t *trow_ptr;
     const int32_t *trow_idx;
     const LevelDev *levels;
@@ -62,6 +63,9 @@ hipError_t launch_getrf_wave(const DevPlan &d, const int32_t *lvl, int nlev, int
 // chunk-k trailing tiles (max_tiles: the most over the wave's levels).
 hipError_t launch_getrf_step(const DevPlan &d, const int32_t *lvl, int nlev, int k, int lds_bytes, hipStream_t s);
 hipError_t launch_getrf_trail(const DevPlan &d, const int32_t *lvl, int nlev, int k, int max_tiles, hipStream_t s);
+// Tiled GETRF of a wave, tile step s (0 <= s < max_nt, the largest number of
+// 16-row tiles of the wave's diagonal blocks).
+hipError_t launch_getrf_tile(const DevPlan &d, const int32_t *lvl, int nlev, int s, int max_nt, hipStream_t st);
 // soff: first workgroup of each of the wave's levels; slots: their total.
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const int32_t *soff, int nlev, int slots,
                                   hipStream_t s);

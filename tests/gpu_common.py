@@ -63,7 +63,9 @@ def check_solves(h, n, rp, ci, v, values_dev, nrhs=1, seed=1):
     assert np.all(eta <= ETA_MAX), "eta %s" % eta
     eta_dev = h.backward_error(values_dev, B, X)
     assert np.all(eta_dev <= ETA_MAX)
-    assert np.allclose(eta_dev, eta, rtol=0.5, atol=1e-16)
+    # both are residuals at roundoff level, summed in different orders: they
+    # agree in magnitude, not digit for digit
+    assert np.allclose(eta_dev, eta, rtol=0.5, atol=1e-15), "eta device %s host %s" % (eta_dev, eta)
     # transpose
     Xt = h.solve_transpose(B)
     xt_ = Xt.cpu().numpy()

@@ -183,6 +183,21 @@ int slu_solve(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t l
 int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs,
                         int64_t ld, void *stream);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): slu_solve (transpose = 0) or slu_solve_transpose
+ * (transpose = 1) with the permuted work block held in a fixed device array
+ * of the library (32 MiB per device, reserved for the life of the process)
+ * instead of the workspace.  The call makes no device allocation or free.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (two streams, two threads) race and must be serialized by the
+ * caller.  Nothing in the array needs to start at zero.  Limits: n <= 4 Mi
+ * rows (SLU_ERR_LIMIT otherwise, returned before any device call); the
+ * right-hand sides are taken min(16, 4 Mi / n) at a time.  Other arguments,
+ * ownership and errors as in slu_solve. */
+int slu_solve_noalloc(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld,
+                      int transpose, void *stream);
+
 /* Normwise backward error per right-hand side on the device,
  * eta_c = ||b_c - op(A) x_c||_inf / (||op(A)||_inf ||x_c||_inf + ||b_c||_inf),
  * op(A) = A or A^T.  values: device float64[nnz_a]; eta: host double[nrhs].

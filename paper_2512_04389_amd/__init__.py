@@ -221,6 +221,16 @@ class SparseLU:
     def solve_transpose(self, B, X=None, stream=None):
         return self._solve(lib.slu_solve_transpose, B, X, stream)
 
+    def solve_noalloc(self, B, X=None, transpose=False, stream=None):
+        """``slu_solve_noalloc``: the solve (or transpose solve) with its
+        work block in the library's fixed device scratch."""
+        t = 1 if transpose else 0
+
+        def fn(h, Bp, Xp, nrhs, ld, st):
+            return lib.slu_solve_noalloc(h, Bp, Xp, nrhs, ld, t, st)
+        fn.__name__ = "slu_solve_noalloc"
+        return self._solve(fn, B, X, stream)
+
     def set_graph(self, enable=True):
         """Capture the factorization's launches into a HIP graph and replay
         it in later factors (see ``slu_set_graph``)."""

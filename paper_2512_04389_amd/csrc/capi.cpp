@@ -123,15 +123,21 @@ hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s
     return hipMemcpyAsync((char *)base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, int trans, hipStream_t s) {
+int solve_check(const slu_handle *h, const double *B, const double *X, int64_t nrhs, int64_t ld) {
     if (!h || (!B && nrhs > 0) || (!X && nrhs > 0) || nrhs < 0) return SLU_ERR_ARG;
     if (!h->bound) return SLU_ERR_STATE;
     if (!h->factored) return SLU_ERR_NOT_FACTORED;
+    if (ld < h->an.n || ld < 1) return SLU_ERR_ARG;
+    return SLU_OK;
+}
+
+// The solve sweeps on the permuted work block d.scratch (n x cols doubles),
+// cols right-hand sides at a time.
+int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B, double *X, int64_t nrhs,
+                 int64_t ld, int trans, hipStream_t s) {
     const slu::Analysis &an = h->an;
-    if (ld < an.n || ld < 1) return SLU_ERR_ARG;
-    const slu::DevPlan &d = h->dev;
-    for (int64_t c0 = 0; c0 < nrhs; c0 += h->solve_cols) {
-        const int nc = (int)std::min<int64_t>(h->solve_cols, nrhs - c0);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += cols) {
+        const int nc = (int)std::min<int64_t>(cols, nrhs - c0);
         hipError_t e = slu::launch_gather_perm(d, B + c0 * ld, ld, nc, s);
         if (hip_failed(e)) return SLU_ERR_HIP;
         // forward sweep wave by wave: the diagonal solves of a wave's levels
@@ -170,6 +176,12 @@ int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t 
         if (hip_failed(e)) return SLU_ERR_HIP;
     }
     return SLU_OK;
+}
+
+int solve_impl(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, int trans, hipStream_t s) {
+    const int rc = solve_check(h, B, X, nrhs, ld);
+    if (rc != SLU_OK) return rc;
+    return solve_sweeps(h, h->dev, h->solve_cols, B, X, nrhs, ld, trans, s);
 }
 
 }  // namespace
@@ -550,6 +562,23 @@ int slu_solve(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t l
 
 int slu_solve_transpose(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, void *stream) {
     return solve_impl(h, B, X, nrhs, ld, 1, (hipStream_t)stream);
+}
+
+int slu_solve_noalloc(slu_handle *h, const double *B, double *X, int64_t nrhs, int64_t ld, int transpose,
+                      void *stream) {
+    if (!h || (transpose != 0 && transpose != 1)) return SLU_ERR_ARG;
+    // the work block must fit the fixed scratch: at least one column of n
+    if (h->an.n > (int64_t)slu::kStaticScratchDoubles) return SLU_ERR_LIMIT;
+    const int rc = solve_check(h, B, X, nrhs, ld);
+    if (rc != SLU_OK) return rc;
+    if (nrhs == 0) return SLU_OK;
+    double *fixed = nullptr;
+    if (hip_failed(slu::static_scratch(&fixed))) return SLU_ERR_HIP;
+    slu::DevPlan d = h->dev;
+    d.scratch = fixed;
+    const int64_t fit = (int64_t)slu::kStaticScratchDoubles / std::max<int64_t>(h->an.n, 1);
+    const int cols = (int)std::min<int64_t>(h->solve_cols, fit);
+    return solve_sweeps(h, d, cols, B, X, nrhs, ld, transpose, (hipStream_t)stream);
 }
 
 int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t nrhs, int64_t ld,

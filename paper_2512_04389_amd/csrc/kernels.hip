@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 namespace slu {
 
@@ -1529,6 +1530,33 @@ hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hi
                                d.stgt, d.maps);
     }
     return hipGetLastError();
+}
+
+// ----------------------------------------------- fixed solve scratch
+// Device scratch of the allocation-free solve (slu_solve_noalloc): the
+// permuted right-hand-side block of one call, n x nc doubles.  Every device
+// the library runs on holds its own copy until the process ends; calls on one
+// device share it.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double **ptr) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the host-side name stands for the array, not its device address:
+        // ask the runtime for this device's copy, once per device
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (double *)p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 // --------------------------------------------------------------------- solve

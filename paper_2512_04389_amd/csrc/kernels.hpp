@@ -46,6 +46,12 @@ struct DevPlan {
 };
 
 constexpr int kSolveCols = 16;
+// Fixed device scratch of slu_solve_noalloc (doubles; 32 MiB), and the
+// device ordinals it is kept for.
+constexpr size_t kStaticScratchDoubles = (size_t)4 << 20;
+constexpr int kMaxDevices = 64;
+// Address of the current device's fixed scratch (looked up once per device).
+hipError_t static_scratch(double **ptr);
 
 hipError_t setup_kernel_attributes();
 hipError_t launch_residual(const DevPlan &d, const double *values, const double *B, int64_t ldb, const double *X,

@@ -1,11 +1,17 @@
 """Benchmark: numerical factorization of blocked sparse LU on one MI355X.
 
-Workload (default): 3D 7-point Laplacian on a 48^3 grid (n = 110,592),
-geometric nested dissection, structure-aware irregular blocking, FP64, one
-right-hand side from a seeded x ~ U[-1, 1].  One "step" is one slu_factor:
-value scatter plus the whole level loop of GETRF / GESSM / TSTRF / SSSSM.
-The analysis (ordering, symbolic fill, blocking) runs once before timing and
-is reported separately, as is the solve with its backward error.
+Headline workload (default): the bordered block-diagonal circuit-like matrix
+(n = 200,000: 64 diagonal blocks with 4 random in-block entries per row and
+a 2,000-row border with 400,000 entries each way), natural order,
+structure-aware irregular blocking (Algorithms 2-3), FP64.  It is the largest
+of the single-GPU configurations (F = 2.9e12 flop on the filled pattern).
+One "step" is one slu_factor: value scatter plus the whole level loop of
+GETRF / GESSM / TSTRF / SSSSM, values already in HBM.  The analysis
+(ordering, symbolic fill, blocking) runs once before timing and is reported
+separately, as are the solves with 8 right-hand sides and their backward
+errors, FP32 factorization + FP64 refinement, the regular-blocking sweep,
+the oracle timed on the host, and the other workloads (3D Laplacian 48^3,
+convection-diffusion 64^3, the 256-system batch) as extra keys.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: the library has no
 multi-GPU path, so only one GPU is measured.
@@ -15,7 +21,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
@@ -24,28 +29,39 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
+METRIC = "numerical-factorization GFLOP/s + ms per factor at backward error <=1e-12, 1 MI355X"
+REGULAR_SWEEP = (200, 300, 500, 1000, 2000, 5000)
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def workload(name):
     import synth
     if name == "lap3d48":
         n, rp, ci, v = synth.laplacian_3d(48)
-        return dict(name="3D 7-point Laplacian 48^3 (n=110592), nested dissection", n=n, rp=rp, ci=ci, v=v,
-                    dims=(48, 48, 48), seed=0)
+        return dict(key=name, name="3D 7-point Laplacian 48^3 (n=110592), nested dissection", n=n, rp=rp, ci=ci,
+                    v=v, dims=(48, 48, 48), ordering="grid_nd", nrhs=1, seed=0)
     if name == "lap2d64":
         n, rp, ci, v = synth.laplacian_2d(64)
-        return dict(name="2D 5-point Laplacian 64^2 (n=4096), nested dissection", n=n, rp=rp, ci=ci, v=v,
-                    dims=(64, 64, 1), seed=0)
+        return dict(key=name, name="2D 5-point Laplacian 64^2 (n=4096), nested dissection", n=n, rp=rp, ci=ci,
+                    v=v, dims=(64, 64, 1), ordering="grid_nd", nrhs=1, seed=0)
     if name == "convdiff64":
         n, rp, ci, v = synth.convection_diffusion_3d(64)
-        return dict(name="3D 7-point convection-diffusion 64^3 (n=262144), nested dissection", n=n, rp=rp,
-                    ci=ci, v=v, dims=(64, 64, 64), seed=0)
+        return dict(key=name, name="3D 7-point convection-diffusion 64^3 (n=262144, Peclet 10 upwind), nested "
+                    "dissection", n=n, rp=rp, ci=ci, v=v, dims=(64, 64, 64), ordering="grid_nd", nrhs=16, seed=0)
     if name == "bbd200k":
         n, rp, ci, v = synth.bbd_circuit()
-        return dict(name="bordered block-diagonal circuit-like matrix (n=200000: 64 diagonal blocks of 4 "
-                         "random in-block entries per row, 2000-row border with 400000 entries each way), "
-                         "natural order", n=n, rp=rp, ci=ci, v=v, dims=None, ordering="natural", seed=0)
+        return dict(key=name, name="bordered block-diagonal circuit-like matrix (n=200000: 64 diagonal blocks of 4 "
+                    "random in-block entries per row, 2000-row border with 400000 entries each way), natural order",
+                    n=n, rp=rp, ci=ci, v=v, dims=None, ordering="natural", nrhs=8, seed=0)
     raise SystemExit("unknown workload %s" % name)
+
+
+def make_handle(W, **kw):
+    import paper_2512_04389_amd as slu
+    return slu.SparseLU(W["n"], W["rp"], W["ci"], ordering=W["ordering"], grid_dims=W["dims"], **kw)
 
 
 def time_factor(h, vals, steps, warmup, torch):
@@ -65,14 +81,27 @@ def time_factor(h, vals, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def time_once(fn, torch):
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(torch.cuda.current_stream())
+    out = fn()
+    e1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), out
+
+
 KERNEL_SOURCES = ("paper_2512_04389_amd/csrc/kernels.hip", "paper_2512_04389_amd/csrc/kernels.hpp",
                   "paper_2512_04389_amd/csrc/analyze.cpp", "paper_2512_04389_amd/csrc/analyze.hpp",
                   "paper_2512_04389_amd/csrc/capi.cpp")   # capi.cpp: the launch sequence
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_getrf_wave_lap3d48.json")
-TRAFFIC_WORKLOAD = "lap3d48"   # the workload the stored counters were taken on
-KERNEL_SYMBOL = {"getrf": ("k_getrf_wave", "k_getrf_step", "k_getrf_trail"),
+KERNEL_SYMBOL = {"getrf": ("k_getrf_wave", "k_getrf_step", "k_getrf_trail", "k_getrf_tile"),
                  "panel": ("k_tri_gather", "k_panel_solve"), "ssssm": ("k_ssssm",)}
 COPY_BYTES = 256 << 20
+
+
+def traffic_file(key):
+    return os.path.join(ROOT, "profiles", "traffic_factor_kernels_%s.json" % key)
 
 
 def kernel_hash():
@@ -84,51 +113,48 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the kernels changed since the counters were taken."""
+def stored_traffic(key, group):
+    """HBM bytes per launch of a kernel group from the committed counter
+    summary of workload `key`, or None when the kernels changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(key)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash() or kernel not in t.get("per_launch_bytes", {}):
+    if t.get("kernel_hash") != kernel_hash() or group not in t.get("per_launch_bytes", {}):
         return None
-    return t["per_launch_bytes"][kernel]
+    return t["per_launch_bytes"][group]
 
 
 def pmc_program(W):
     """Program run under rocprofv3 --pmc: a plain copy of COPY_BYTES (the
     calibration of the byte counters), then one factorization."""
     import torch
-
-    import paper_2512_04389_amd as slu
     x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     y.copy_(x)
     torch.cuda.synchronize()
-    h = slu.SparseLU(W["n"], W["rp"], W["ci"], ordering=W.get("ordering", "grid_nd"), grid_dims=W["dims"]).bind()
+    h = make_handle(W).bind()
     vals = torch.from_numpy(W["v"]).cuda()
     h.factor(vals)
     torch.cuda.synchronize()
-    print("[bench] pmc program done", file=sys.stderr, flush=True)
+    log("pmc program done")
 
 
 def pmc_summarize(fetch_csv, write_csv, out):
-    """Per-launch HBM bytes of the factor kernels from two counter runs
+    """Per-launch HBM bytes of the factor kernel groups from two counter runs
     (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled so that the
     calibration copy reads / writes exactly COPY_BYTES."""
     import csv
 
     def load(path, counter):
-        rows = list(csv.DictReader(open(path)))
         per = {}
-        for r in rows:
+        for r in csv.DictReader(open(path)):
             if r.get("Counter_Name") != counter:
                 continue
-            per.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), 0.0)
-            per[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
+            k = (r["Kernel_Name"], r["Dispatch_Id"])
+            per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
         return per
 
     fetch = load(fetch_csv, "FETCH_SIZE")
@@ -161,17 +187,35 @@ def pmc_summarize(fetch_csv, write_csv, out):
     print(json.dumps(res))
 
 
-def cpu_baseline(W, budget_flops):
+def host_record():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": affinity}
+
+
+def cpu_baseline(W, perm, budget_flops):
     """The oracle's right-looking LU on the first kmax pivots of the same
-    matrix (a partial factorization), single thread."""
+    matrix and order (a partial factorization), one thread."""
     import ctypes
 
     import numpy as np
 
-    from oracle import metrics, numeric, ordering, symbolic
+    from oracle import metrics, numeric, symbolic
     n, rp, ci, v = W["n"], W["rp"], W["ci"], W["v"]
-    perm = ordering.nd_grid(W["dims"])
+    t0 = time.perf_counter()
     cp, ri = symbolic.symbolic(n, rp, ci, perm)
+    sym_s = time.perf_counter() - t0
     c = np.diff(cp) - 1
     cum = np.cumsum(c + 2 * c * c)
     kmax = int(np.searchsorted(cum, budget_flops, side="right"))
@@ -186,22 +230,144 @@ def cpu_baseline(W, budget_flops):
     rc = lib.oracle_factor(n, kmax, P(cpc), P(ric), P(lval), P(uval))
     dt = time.perf_counter() - t0
     assert rc == 0
+    host = host_record()
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d pivots of the same matrix (partial right-looking LU, %.3g flop of %.3g), "
-                      "%.1f s on %s" % (kmax, n, flops, float(cum[-1]), dt, platform.processor() or "host cpu"),
-            "seconds": dt}
+            "sample": "first %d of %d pivots of the same matrix and order (the oracle's partial right-looking LU "
+                      "on S, %.3g of its %.3g flop), %.1f s on one thread of %s (%s CPUs)"
+                      % (kmax, n, flops, float(cum[-1]), dt, host["cpu_model"], host["nproc"]),
+            "seconds": dt, "symbolic_s": sym_s, "host": host}
 
 
-def batch_bench(args):
-    """Batch of independent systems (2D and 3D Laplacian-like grids with
-    perturbed values, n from 2k to 20k): one handle, factor launch by
-    launch and by graph replay, FP64 and FP32 + refinement."""
+def oracle_perm(W, h):
+    from oracle import ordering
+    if W["ordering"] == "grid_nd":
+        return ordering.nd_grid(W["dims"])
+    if W["ordering"] == "natural":
+        return ordering.natural(W["n"])
+    return h.perm()          # an order the library computed: the oracle consumes it
+
+
+def solve_block(W, nrhs, torch):
     import numpy as np
-    import torch
+
+    import synth
+    xt = synth.random_x(W["n"], nrhs, seed=W["seed"] + 1)
+    b = synth.csr_matvec(W["n"], W["rp"], W["ci"], W["v"], xt)
+    return torch.from_numpy(np.ascontiguousarray(b)).cuda(), xt
+
+
+def regular_sweep(W, vals, B, sizes, steps, torch):
+    import numpy as np
+    out = []
+    for bs in sizes:
+        if bs >= W["n"]:
+            continue
+        t0 = time.perf_counter()
+        hr = make_handle(W, blocking="regular", block_size=bs)
+        an_s = time.perf_counter() - t0
+        hr.bind()
+        rms, _ = time_factor(hr, vals, steps, 1, torch)
+        X = hr.solve(B)
+        eta = float(np.max(hr.backward_error(vals, B, X)))
+        out.append({"block": bs, "levels": hr.info()["nblocks"], "ms": rms, "eta": eta, "analyze_s": an_s})
+        log("regular b=%d: %.2f ms" % (bs, rms))
+        hr.close()
+        del hr
+        torch.cuda.empty_cache()
+    return out
+
+
+def measure(W, args, torch, full):
+    """Factor timing and its companions on workload W; `full` adds the
+    per-kernel roofline, FP32 + refinement, the regular sweep and the oracle."""
+    import numpy as np
+    log("workload %s" % W["name"])
+    t0 = time.perf_counter()
+    h = make_handle(W)
+    analyze_s = time.perf_counter() - t0
+    info = h.info()
+    h.bind()
+    vals = torch.from_numpy(W["v"]).cuda()
+    F = info["flops"]
+    log("analyzed in %.2f s: levels %d, waves %d, nnz(S) %d, F %.4g" %
+        (analyze_s, info["nblocks"], info["waves"], info["nnz_s"], F))
+    steps = args.steps if full else max(3, args.steps // 2)
+    ms, wall_ms = time_factor(h, vals, steps, args.warmup, torch)
+    singles = sorted(time_once(lambda: h.factor(vals), torch)[0] for _ in range(max(5, steps)))
+    res = {"workload": W["name"], "n": W["n"], "nnz_a": info["nnz_a"], "nnz_s": info["nnz_s"], "flops": F,
+           "levels": info["nblocks"], "waves": info["waves"], "rounds": info["rounds"],
+           "nonempty_blocks": info["nonempty_blocks"], "ms": ms, "wall_ms": wall_ms,
+           "median_ms": singles[len(singles) // 2], "min_ms": singles[0], "gflops": F / (ms * 1e-3) / 1e9,
+           "analyze_s": analyze_s}
+    B, xt = solve_block(W, W["nrhs"], torch)
+    h.solve(B)
+    solve_ms, X = time_once(lambda: h.solve(B), torch)
+    eta = h.backward_error(vals, B, X)
+    res.update(nrhs=W["nrhs"], solve_ms=solve_ms, backward_error=float(np.max(eta)),
+               eta_ok=bool(np.all(eta <= 1e-12)),
+               forward_error=float(torch.max(torch.abs(X.cpu() - torch.from_numpy(xt))).item()))
+    if full:
+        h.set_profiling(True)
+        h.factor(vals)
+        kt = h.kernel_times()
+        h.set_profiling(False)
+        res["per_kernel_ms"] = {k: {"ms": v[0], "launches": v[1]} for k, v in kt.items()}
+        res["algorithmic_flops"] = {"getrf": info["flops_getrf"], "panel": info["flops_panel"],
+                                    "ssssm": info["flops_ssssm"]}
+        # FP32 factorization + FP64 refinement with the same right-hand sides
+        lv64, _ = h.factors()
+        h.set_precision("fp32")
+        ms32, _ = time_factor(h, vals, max(2, steps // 2), 1, torch)
+        lv32, _ = h.factors()
+        big = np.abs(lv64) > 1e-6 * np.max(np.abs(lv64))
+        fdiff = float(np.max(np.abs(lv32[big] - lv64[big]) / np.abs(lv64[big])))
+        h.solve_refined(vals, B)
+        rms, (Xr, its, eta_r, conv) = time_once(lambda: h.solve_refined(vals, B), torch)
+        res["fp32_ir"] = {"factor_ms": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "refined_solve_ms": rms,
+                          "corrections": its, "eta": float(np.max(eta_r)), "converged": bool(conv),
+                          "factor_max_rel_diff_vs_fp64": fdiff, "factor_plus_solve_ms": ms32 + rms,
+                          "fp64_factor_plus_solve_ms": ms + solve_ms, "nrhs": W["nrhs"]}
+        h.set_precision("fp64")
+        perm = oracle_perm(W, h)
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    sizes = [int(x) for x in args.regular.split(",") if x] if full else [500]
+    res["regular"] = regular_sweep(W, vals, B, sizes, max(2, steps // 2), torch)
+    if res["regular"]:
+        best = min(res["regular"], key=lambda r: r["ms"])
+        res["regular_best"] = {"block": best["block"], "ms": best["ms"], "irregular_speedup": best["ms"] / ms}
+    if full and not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(W, perm, args.cpu_budget)
+    return res
+
+
+def rooflines(res, traffic_key):
+    """Achieved algorithmic flops per launch / average launch time per kernel
+    group (HIP events around every launch on the launch stream)."""
+    bounds = {"getrf": "mfma", "panel": "mfma", "ssssm": "mfma"}
+    out = {}
+    for k in ("getrf", "panel", "ssssm"):
+        kms, kn = res["per_kernel_ms"][k]["ms"], res["per_kernel_ms"][k]["launches"]
+        if kms <= 0 or kn <= 0:
+            continue
+        fl = res["algorithmic_flops"][k]
+        ach = fl / (kms * 1e-3) / 1e12
+        out[k] = {"bound": bounds[k], "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                  "frac": ach / PEAK_FP64_TFLOPS, "traffic": stored_traffic(traffic_key, k),
+                  "avg_launch_us": kms * 1e3 / kn, "launches": kn, "algorithmic_flops_per_launch": fl / kn}
+    return out
+
+
+def batch_measure(nsys, args, torch):
+    """Batch of independent systems (2D and 3D Laplacian-like grids with
+    perturbed values, n from 2k to 20k): one handle, factor launch by launch
+    and by graph replay, FP64 and FP32 + refinement."""
+    import numpy as np
 
     import paper_2512_04389_amd as slu
     import synth
-    nsys = args.batch
     sy = [synth.batch_system(s) for s in range(nsys)]
     t0 = time.perf_counter()
     h = slu.SparseLU.batch([(x[0], x[1], x[2]) for x in sy], ordering="grid_nd", grid_dims=[x[4] for x in sy])
@@ -210,36 +376,32 @@ def batch_bench(args):
     info = h.info()
     vals = torch.from_numpy(np.concatenate([x[3] for x in sy])).cuda()
     F = info["flops"]
-    ms, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    steps = max(3, args.steps // 2)
+    ms, _ = time_factor(h, vals, steps, args.warmup, torch)
     h.set_graph(True)
-    ms_g, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    ms_g, _ = time_factor(h, vals, steps, args.warmup, torch)
+    h.set_graph(False)
     xs = synth.random_x(h.n, 1, seed=0)[:, 0]
+    offs = np.cumsum([0] + [x[0] for x in sy[:-1]])
     B = torch.from_numpy(np.concatenate([synth.csr_matvec(x[0], x[1], x[2], x[3], xs[o:o + x[0]])
-                                         for x, o in zip(sy, np.cumsum([0] + [x[0] for x in sy[:-1]]))])).cuda()
-    X = h.solve(B)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    X = h.solve(B)
-    e1.record(st)
-    torch.cuda.synchronize()
-    solve_ms = e0.elapsed_time(e1)
+                                         for x, o in zip(sy, offs)])).cuda()
+    h.solve(B)
+    solve_ms, X = time_once(lambda: h.solve(B), torch)
     eta = float(h.backward_error(vals, B, X)[0])
     h.set_precision("fp32")
-    ms32, _ = time_factor(h, vals, args.steps, args.warmup, torch)
+    ms32, _ = time_factor(h, vals, steps, 1, torch)
     Xr, its, eta_r, conv = h.solve_refined(vals, B)
-    line = {"metric": "batched factorization GFLOP/s, 1 MI355X", "value": F / (ms_g * 1e-3) / 1e9,
-            "unit": "GFLOP/s", "config": {"workload": "%d independent systems (2D 5-point / 3D 7-point, "
-                                                      "n 2k-20k, perturbed values), nested dissection" % nsys,
-                                          "n_total": h.n, "nnz_s": info["nnz_s"], "flops": F,
-                                          "levels": info["nblocks"], "waves": info["waves"],
-                                          "rounds": info["rounds"]},
-            "analyze_s": analyze_s, "ms_launches": ms, "ms_graph": ms_g, "solve_ms": solve_ms, "eta": eta,
-            "fp32": {"ms_graph": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "corrections": its,
-                     "eta": float(np.max(eta_r)), "converged": bool(conv)}}
-    print(json.dumps(line), flush=True)
+    out = {"workload": "%d independent systems (2D 5-point / 3D 7-point, n 2k-20k, perturbed values), nested "
+                       "dissection" % nsys, "n_total": h.n, "nnz_s": info["nnz_s"], "flops": F,
+           "levels": info["nblocks"], "waves": info["waves"], "rounds": info["rounds"], "analyze_s": analyze_s,
+           "ms_launches": ms, "ms_graph": ms_g, "gflops": F / (min(ms, ms_g) * 1e-3) / 1e9,
+           "solve_ms": solve_ms, "eta": eta,
+           "fp32": {"ms": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "corrections": its,
+                    "eta": float(np.max(eta_r)), "converged": bool(conv)}}
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -247,179 +409,58 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lap3d48")
-    ap.add_argument("--regular", type=int, default=500, help="regular block size to compare (0: skip)")
+    ap.add_argument("--workload", default="bbd200k")
+    ap.add_argument("--regular", default=",".join(str(b) for b in REGULAR_SWEEP),
+                    help="regular block sizes to compare (comma separated, empty: none)")
+    ap.add_argument("--extra", default="lap3d48,convdiff64,batch256",
+                    help="further workloads reported as extra keys (comma separated, empty: none)")
     ap.add_argument("--cpu-budget", type=float, default=1.5e10, help="oracle flops timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=0, help="time a batch of this many systems instead")
     ap.add_argument("--pmc-program", action="store_true", help="calibration copy + one factor (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the per-launch HBM traffic summary from two counter runs")
+                    help="write the per-launch HBM traffic summary of --workload from two counter runs")
     args = ap.parse_args()
     if args.pmc_summarize:
-        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], TRAFFIC_FILE)
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], traffic_file(args.workload))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import paper_2512_04389_amd as slu
-    import synth
+    import paper_2512_04389_amd  # noqa: F401  (fails loudly without the built library)
 
     assert torch.cuda.is_available(), "no HIP device"
-    if args.batch > 0:
-        batch_bench(args)
-        return
     W = workload(args.workload)
     if args.pmc_program:
         pmc_program(W)
         return
-    n = W["n"]
-    print("[bench] workload %s" % W["name"], file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    order = W.get("ordering", "grid_nd")
-    h = slu.SparseLU(n, W["rp"], W["ci"], ordering=order, grid_dims=W["dims"])
-    analyze_s = time.perf_counter() - t0
-    info = h.info()
-    h.bind()
-    vals = torch.from_numpy(W["v"]).cuda()
-    print("[bench] analyzed in %.2f s: levels %d, nnz(S) %d, F %.4g; timing factor" %
-          (analyze_s, info["nblocks"], info["nnz_s"], info["flops"]), file=sys.stderr, flush=True)
-    ms, wall_ms = time_factor(h, vals, args.steps, args.warmup, torch)
-    F = info["flops"]
-    gflops = F / (ms * 1e-3) / 1e9
-    # each factor timed on its own as well: median and minimum
-    singles = []
-    for _ in range(max(10, args.steps)):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(torch.cuda.current_stream())
-        h.factor(vals)
-        e1.record(torch.cuda.current_stream())
-        torch.cuda.synchronize()
-        singles.append(e0.elapsed_time(e1))
-    singles.sort()
-    median_ms = singles[len(singles) // 2]
-
-    # per-kernel times (HIP events around every launch, separate pass)
-    h.set_profiling(True)
-    h.factor(vals)
-    kt = h.kernel_times()
-    h.set_profiling(False)
-    kflops = {"getrf": info["flops_getrf"], "panel": info["flops_panel"], "ssssm": info["flops_ssssm"]}
-    per_kernel = {}
-    for k, (kms, nl) in kt.items():
-        ent = {"ms": kms, "launches": nl}
-        if k in kflops and kms > 0:
-            ent["algorithmic_flops"] = kflops[k]
-            ent["tflops"] = kflops[k] / (kms * 1e-3) / 1e12
-        per_kernel[k] = ent
-    # algorithmic bytes of GETRF: every stored entry of the diagonal blocks
-    # read and written once (FP64)
-    bptr = h.blocking()
-    bsz = np.diff(bptr).astype(np.float64)
-    getrf_bytes = float(np.sum(bsz * bsz)) * 16.0
-    bounds = {"getrf": "alu", "panel": "mfma", "ssssm": "mfma"}
-    rooflines = {}
-    for k in ("getrf", "panel", "ssssm"):
-        kms, kn = kt[k]
-        if kms <= 0:
-            continue
-        ach = kflops[k] / (kms * 1e-3) / 1e12
-        rooflines[k] = {"bound": bounds[k], "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                        "frac": ach / PEAK_FP64_TFLOPS, "avg_launch_us": kms * 1e3 / max(kn, 1), "launches": kn,
-                        "traffic": stored_traffic(k) if args.workload == TRAFFIC_WORKLOAD else None}
-    rooflines["getrf"]["hbm_achieved_GBs"] = getrf_bytes / (kt["getrf"][0] * 1e-3) / 1e9
-    rooflines["getrf"]["hbm_frac"] = rooflines["getrf"]["hbm_achieved_GBs"] / PEAK_HBM_GBS
-    rooflines["getrf"]["algorithmic_bytes_per_launch"] = getrf_bytes / max(kt["getrf"][1], 1)
-    dom = max(rooflines, key=lambda k: kt[k][0])
-    roofline = dict(rooflines[dom])
+    res = measure(W, args, torch, full=True)
+    rl = rooflines(res, W["key"])
+    dom = max(rl, key=lambda k: res["per_kernel_ms"][k]["ms"])
+    roofline = dict(rl[dom])
     roofline["kernel"] = "+".join(KERNEL_SYMBOL[dom])
-
-    # solve and backward error (gate), not part of the metric
-    xt = synth.random_x(n, 1, seed=W["seed"])[:, 0]
-    b = synth.csr_matvec(n, W["rp"], W["ci"], W["v"], xt)
-    B = torch.from_numpy(b).cuda()
-    X = h.solve(B)
-    torch.cuda.synchronize()
-    s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    X = h.solve(B)
-    e1.record(s)
-    torch.cuda.synchronize()
-    solve_ms = e0.elapsed_time(e1)
-    eta = float(h.backward_error(vals, B, X)[0])
-    fwd_err = float(torch.max(torch.abs(X.cpu() - torch.from_numpy(xt))).item())
-
-    # FP32 factorization (Schur updates on FP32 MFMA) + FP64 refinement
-    h.set_profiling(False)
-    lv64, uv64 = h.factors()
-    h.set_precision("fp32")
-    ms32, _ = time_factor(h, vals, max(2, args.steps // 2), 1, torch)
-    lv32, uv32 = h.factors()
-    big = np.abs(lv64) > 1e-6 * np.max(np.abs(lv64))
-    fdiff = float(np.max(np.abs(lv32[big] - lv64[big]) / np.abs(lv64[big])))
-    Xr, its, eta_r, conv = h.solve_refined(vals, B)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(torch.cuda.current_stream())
-    Xr, its, eta_r, conv = h.solve_refined(vals, B)
-    e1.record(torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    refine_ms = e0.elapsed_time(e1)
-    fp32_ir = {"factor_ms": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "refined_solve_ms": refine_ms,
-               "corrections": its, "eta": float(np.max(eta_r)), "converged": bool(conv),
-               "factor_max_rel_diff_vs_fp64": fdiff,
-               "factor_plus_solve_ms": ms32 + refine_ms, "fp64_factor_plus_solve_ms": ms + solve_ms}
-    h.set_precision("fp64")
-
-    out_regular = None
-    if args.regular > 0:
-        print("[bench] regular blocking b=%d" % args.regular, file=sys.stderr, flush=True)
-        hr = slu.SparseLU(n, W["rp"], W["ci"], ordering=order, grid_dims=W["dims"], blocking="regular",
-                          block_size=args.regular).bind()
-        rms, _ = time_factor(hr, vals, max(2, args.steps // 2), 1, torch)
-        Xr = hr.solve(B)
-        eta_r = float(hr.backward_error(vals, B, Xr)[0])
-        out_regular = {"block": args.regular, "levels": hr.info()["nblocks"], "ms": rms,
-                       "gflops": F / (rms * 1e-3) / 1e9, "eta": eta_r}
-        hr.close()
-        del hr
-
-    cpu = None
-    if W["dims"] is None and not args.no_cpu_baseline:
-        # the oracle's symbolic fill runs over the whole matrix before the
-        # bounded numeric sample; on this workload that alone is too large
-        print("[bench] cpu baseline skipped for this workload", file=sys.stderr, flush=True)
-    elif not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(W, args.cpu_budget)
-
+    extras = {}
+    for name in [x for x in args.extra.split(",") if x]:
+        if name.startswith("batch"):
+            extras[name] = batch_measure(int(name[5:] or 256), args, torch)
+        else:
+            extras[name] = measure(workload(name), args, torch, full=False)
+    cfg = {k: res[k] for k in ("n", "nnz_a", "nnz_s", "flops", "levels", "waves", "rounds", "nonempty_blocks")}
+    cfg["workload"] = W["name"] + ", irregular blocking (Algorithm 3), FP64, %d RHS" % W["nrhs"]
+    cfg["parallelism"] = "single GPU"
     line = {
-        "metric": "numerical-factorization GFLOP/s + ms per factor at backward error <=1e-12, 1 MI355X",
-        "value": gflops, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": W["name"] + ", irregular blocking (Algorithm 3), FP64, 1 RHS",
-                   "n": n, "nnz_a": info["nnz_a"], "nnz_s": info["nnz_s"], "flops": F,
-                   "levels": info["nblocks"], "nonempty_blocks": info["nonempty_blocks"],
-                   "ssssm_tasks": info["ssssm_tasks"], "parallelism": "single GPU"},
-        "wall_ms_per_step": wall_ms, "median_ms": median_ms, "min_ms": singles[0],
-        "backward_error": eta, "eta_ok": eta <= 1e-12, "forward_error": fwd_err,
-        "analyze_s": analyze_s, "solve_ms": solve_ms,
-        "per_kernel": per_kernel,
-        "roofline": roofline,
-        "rooflines": rooflines,
-        "regular": out_regular,
-        "fp32_ir": fp32_ir,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": res["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
+        "wall_ms_per_step": res["wall_ms"], "median_ms": res["median_ms"], "min_ms": res["min_ms"],
+        "backward_error": res["backward_error"], "eta_ok": res["eta_ok"], "forward_error": res["forward_error"],
+        "analyze_s": res["analyze_s"], "solve_ms": res["solve_ms"], "nrhs": res["nrhs"],
+        "per_kernel": res["per_kernel_ms"], "roofline": roofline, "rooflines": rl,
+        "regular": res["regular"], "regular_best": res.get("regular_best"), "fp32_ir": res["fp32_ir"],
+        "cpu_baseline": res.get("cpu_baseline"), "extra": extras,
     }
     print(json.dumps(line), flush=True)
 

@@ -68,6 +68,10 @@ typedef struct slu_handle slu_handle;
 #define SLU_ORDER_NATURAL 0       /* identity                                */
 #define SLU_ORDER_GRID_ND 1       /* geometric nested dissection of a grid   */
 #define SLU_ORDER_USER 2          /* caller's permutation (new -> old)       */
+#define SLU_ORDER_GRAPH_ND 3      /* graph nested dissection of A + A^T: dense
+                                     vertices last, connected components
+                                     apart, level-structure cuts with minimum
+                                     vertex-cover separators; deterministic  */
 
 /* schedules of the level loop */
 #define SLU_SCHEDULE_WAVES 0      /* levels of equal height in the block
@@ -135,7 +139,8 @@ int slu_analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx,
  * order n[q] and its CSR pattern rowptr[q], colidx[q] (host arrays, copied).
  * The systems are stacked block-diagonally in the given order (rows and
  * columns of system q follow those of systems 0..q-1); each keeps its own
- * ordering (SLU_ORDER_GRID_ND with grid_dims[3q..3q+2], or SLU_ORDER_NATURAL)
+ * ordering (SLU_ORDER_GRID_ND with grid_dims[3q..3q+2], SLU_ORDER_GRAPH_ND or
+ * SLU_ORDER_NATURAL)
  * and its own blocking (Algorithm 3 on its own block pointer, or regular
  * blocks restarting at every system).  Levels of different systems with
  * equal dependency height share the wave launches, and the Schur updates of
@@ -226,7 +231,8 @@ int slu_value_gradient(slu_handle *h, const double *G, const double *X, int64_t 
  * launch-by-launch path.  enable = 0 releases the graph. */
 int slu_set_graph(slu_handle *h, int enable);
 
-/* GETRF launch shape (Algorithm 1, the factorization of the diagonal
+/* GETRF launch shape of the waves that do not take the tiled GETRF
+ * (slu_set_getrf_tiled; Algorithm 1, the factorization of the diagonal
  * blocks).  A wave whose chunked diagonal blocks (more than 128 rows) include
  * one with trailing work of at least min_work, counted as the sum over its
  * column chunks of (coupled rows)^2, is factored chunk by chunk in two
@@ -246,8 +252,9 @@ int slu_set_getrf_split(slu_handle *h, double min_work);
  * tile per workgroup: the panel tiles are solved by products with the
  * inverted diagonal tile of the previous step and every trailing tile is
  * updated with FP64 MFMA; the diagonal tile of the step is then factored and
- * inverted.  min_rows = 0 (the default) keeps the chunked GETRF on every
- * wave.  Same factors as the other GETRF paths up to rounding.  A captured
+ * inverted.  Default 1 (every wave); min_rows = 0 keeps the one-launch or
+ * split chunked GETRF (slu_set_getrf_split) on every wave whose chunks fit
+ * the LDS (waves with larger dense blocks take the tiled GETRF regardless).  Same factors as the other GETRF paths up to rounding.  A captured
  * graph is released and recaptured.  SLU_ERR_ARG for a negative min_rows. */
 int slu_set_getrf_tiled(slu_handle *h, int min_rows);
 

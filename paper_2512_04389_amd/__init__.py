@@ -76,6 +76,8 @@ class SparseLU:
             dims = tuple(int(v) for v in grid_dims) + (1,) * (3 - len(grid_dims))
             for d in range(3):
                 opt.grid_dims[d] = dims[d]
+        elif ordering == "graph_nd":
+            opt.ordering = _abi.SLU_ORDER_GRAPH_ND
         elif ordering == "user":
             opt.ordering = SLU_ORDER_USER
             self._perm_in = np.ascontiguousarray(perm, dtype=np.int32)
@@ -108,7 +110,8 @@ class SparseLU:
         opt.blocking = {"irregular": SLU_BLOCK_IRREGULAR, "regular": SLU_BLOCK_REGULAR}[blocking]
         opt.regular_block = int(block_size)
         opt.schedule = {"waves": _abi.SLU_SCHEDULE_WAVES, "levels": _abi.SLU_SCHEDULE_LEVELS}[schedule]
-        opt.ordering = {"natural": SLU_ORDER_NATURAL, "grid_nd": SLU_ORDER_GRID_ND}[ordering]
+        opt.ordering = {"natural": SLU_ORDER_NATURAL, "grid_nd": SLU_ORDER_GRID_ND,
+                        "graph_nd": _abi.SLU_ORDER_GRAPH_ND}[ordering]
         dims = None
         if ordering == "grid_nd":
             dims = np.ascontiguousarray([tuple(int(x) for x in g) + (1,) * (3 - len(g)) for g in grid_dims],

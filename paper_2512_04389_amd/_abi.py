@@ -30,6 +30,7 @@ SLU_ERR_LIMIT = -11
 SLU_ORDER_NATURAL = 0
 SLU_ORDER_GRID_ND = 1
 SLU_ORDER_USER = 2
+SLU_ORDER_GRAPH_ND = 3
 SLU_BLOCK_IRREGULAR = 0
 SLU_BLOCK_REGULAR = 1
 SLU_SCHEDULE_WAVES = 0

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libslu.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("analyze.cpp", "capi.cpp", "kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("analyze.cpp", "nd_graph.cpp", "capi.cpp", "kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

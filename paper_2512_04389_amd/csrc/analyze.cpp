@@ -291,6 +291,8 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         const int64_t nx = opt.grid_dims[0], ny = opt.grid_dims[1], nz = opt.grid_dims[2];
         if (nx < 1 || ny < 1 || nz < 1 || nx * ny * nz != n) return SLU_ERR_ARG;
         nd_grid_order((int32_t)nx, (int32_t)ny, (int32_t)nz, &an.perm);
+    } else if (opt.ordering == SLU_ORDER_GRAPH_ND) {
+        nd_graph_order(n, rowptr, colidx, &an.perm);
     } else if (opt.ordering == SLU_ORDER_USER) {
         if (!opt.user_perm && n > 0) return SLU_ERR_ARG;
         an.perm.assign(opt.user_perm, opt.user_perm + n);

@@ -168,6 +168,11 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
 // Geometric nested dissection of an nx x ny x nz grid (new -> old).
 void nd_grid_order(int32_t nx, int32_t ny, int32_t nz, std::vector<int32_t> *perm);
 
+// Graph nested dissection of the pattern of A + A^T (new -> old): dense
+// vertices last, connected components apart, level-structure cuts with
+// minimum vertex covers as separators (nd_graph.cpp).
+void nd_graph_order(int64_t n, const int64_t *rowptr, const int32_t *colidx, std::vector<int32_t> *perm);
+
 // Host threads of the analysis' parallel parts (0: hardware count, at most 16).
 void set_host_threads(int threads);
 

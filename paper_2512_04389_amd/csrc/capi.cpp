@@ -41,7 +41,7 @@ struct slu_handle {
     double getrf_split_work = 2e5;
     // waves whose largest diagonal block has at least this many rows take
     // the tiled GETRF (0: none)
-    int getrf_tiled_rows = 0;
+    int getrf_tiled_rows = 1;
 };
 
 namespace {
@@ -223,8 +223,6 @@ int analyze_into(int64_t n, const int64_t *rowptr, const int32_t *colidx, const 
                     h->solve_cols = nc;
                     break;
                 }
-            for (const slu::LevelDev &L : h->an.levels)
-                if (L.lds_getrf > 160 * 1024) rc = SLU_ERR_LIMIT;
             if (h->solve_cols < 1) rc = SLU_ERR_LIMIT;
             plan_workspace(h);
         }
@@ -265,7 +263,8 @@ int slu_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowp
         o = *opt;
     else
         slu_default_options(&o);
-    if (o.ordering != SLU_ORDER_NATURAL && o.ordering != SLU_ORDER_GRID_ND) return SLU_ERR_ARG;
+    if (o.ordering != SLU_ORDER_NATURAL && o.ordering != SLU_ORDER_GRID_ND && o.ordering != SLU_ORDER_GRAPH_ND)
+        return SLU_ERR_ARG;
     if (o.ordering == SLU_ORDER_GRID_ND && !grid_dims) return SLU_ERR_ARG;
     try {
         std::vector<int64_t> seg(1, 0), rp(1, 0);
@@ -288,6 +287,8 @@ int slu_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowp
                 const int32_t *g = grid_dims + 3 * q;
                 if (g[0] < 1 || g[1] < 1 || g[2] < 1 || (int64_t)g[0] * g[1] * g[2] != ns) return SLU_ERR_ARG;
                 slu::nd_grid_order(g[0], g[1], g[2], &p1);
+            } else if (o.ordering == SLU_ORDER_GRAPH_ND) {
+                slu::nd_graph_order(ns, rowptr[q], colidx[q], &p1);
             } else {
                 p1.resize(ns);
                 for (int64_t i = 0; i < ns; ++i) p1[i] = (int32_t)i;
@@ -448,7 +449,11 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     for (const slu::WaveInfo &w : an.waves) {
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
-        if (h->getrf_tiled_rows > 0 && w.max_b >= h->getrf_tiled_rows && nlev <= 65535) {
+        // the tiled GETRF when selected, and for waves whose chunked GETRF
+        // would not fit the LDS
+        const bool chunk_fits = w.lds_getrf <= 160 * 1024;
+        if ((h->getrf_tiled_rows > 0 && w.max_b >= h->getrf_tiled_rows) || !chunk_fits) {
+            if (nlev > 65535) return SLU_ERR_LIMIT;
             const int max_nt = (w.max_b + 15) / 16;
             for (int k = 0; k < max_nt; ++k)
                 SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));

@@ -18,12 +18,17 @@ def announce(msg):
     sys.stdout.flush()
 
 
-def oracle_perm(n, kw):
+def oracle_perm(n, kw, h=None):
     o = kw.get("ordering", "natural")
     if o == "grid_nd":
         return ordering.nd_grid(kw["grid_dims"])
     if o == "user":
         return np.asarray(kw["perm"], dtype=np.int32)
+    if o == "graph_nd":
+        # the library's graph nested dissection: the oracle consumes the order
+        perm = h.perm()
+        assert ordering.is_permutation(perm, n)
+        return perm
     return ordering.natural(n)
 
 
@@ -37,7 +42,7 @@ def factor_close(got, ref):
 
 
 def check_factors(h, n, rp, ci, v, kw, oracle_factors=None):
-    perm = oracle_perm(n, kw)
+    perm = oracle_perm(n, kw, h)
     cp, ri = symbolic.symbolic(n, rp, ci, perm)
     hcp, hri = h.pattern()
     assert np.array_equal(hcp, cp) and np.array_equal(hri, ri), "pattern differs from oracle"

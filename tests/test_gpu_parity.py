@@ -80,6 +80,19 @@ def test_random_unsymmetric_natural():
     run_case("random-600-regular-160", n, rp, ci, v, blocking="regular", block_size=160)
 
 
+@pytest.mark.parametrize("case", ["lap3d-12", "convdiff-16", "bbd-2400", "random-600"])
+def test_graph_nested_dissection(case):
+    if case == "lap3d-12":
+        n, rp, ci, v = synth.laplacian_3d(12)
+    elif case == "convdiff-16":
+        n, rp, ci, v = synth.convection_diffusion_3d(16)
+    elif case == "bbd-2400":
+        n, rp, ci, v = synth.bbd_circuit(n=2400, nblocks=8, border=80, border_nnz=12000, seed=4)
+    else:
+        n, rp, ci, v = _dd_random(600, 0.01, seed=5)
+    run_case("graph-nd-" + case, n, rp, ci, v, nrhs=2, ordering="graph_nd")
+
+
 def test_random_user_perm():
     n, rp, ci, v = _dd_random(400, 0.02, seed=6, sym_pattern=True)
     perm = np.random.default_rng(1).permutation(n).astype(np.int32)
@@ -147,6 +160,7 @@ def test_split_getrf_matches_one_launch(case):
         opts = dict(blocking="regular", block_size=300)
     announce("split GETRF " + case)
     h = slu.SparseLU(n, rp, ci, **opts).bind()
+    h.set_getrf_tiled(0)
     assert max(np.diff(h.blocking())) > 128
     vals = torch.from_numpy(v).cuda()
     h.factor(vals)
@@ -166,6 +180,28 @@ def test_split_getrf_matches_one_launch(case):
     check_factors(h, n, rp, ci, v, opts)
     with pytest.raises(slu.SluError):
         h.set_getrf_split(-1.0)
+
+
+@pytest.mark.parametrize("case", ["lap3d-12", "convdiff-14-regular-200", "bbd-2400"])
+def test_chunked_getrf_paths(case):
+    # slu_set_getrf_tiled(0): the one-launch GETRF (dense blocks of at most
+    # 128 rows in LDS, chunked above) on every wave
+    import paper_2512_04389_amd as slu
+    if case == "lap3d-12":
+        n, rp, ci, v = synth.laplacian_3d(12)
+        opts = dict(ordering="grid_nd", grid_dims=(12, 12, 12))
+    elif case.startswith("convdiff"):
+        n, rp, ci, v = synth.convection_diffusion_3d(14)
+        opts = dict(ordering="grid_nd", grid_dims=(14, 14, 14), blocking="regular", block_size=200)
+    else:
+        n, rp, ci, v = synth.bbd_circuit(n=2400, nblocks=8, border=80, border_nnz=2000, seed=4)
+        opts = {}
+    announce("chunked GETRF " + case)
+    h = slu.SparseLU(n, rp, ci, **opts).bind()
+    h.set_getrf_tiled(0)
+    vals = torch.from_numpy(v).cuda()
+    h.factor(vals)
+    check_factors(h, n, rp, ci, v, opts)
 
 
 def test_determinism_and_refactor():

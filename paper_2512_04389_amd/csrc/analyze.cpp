@@ -611,7 +611,6 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
         an.sbatch.push_back(L.sch_end);
         an.sbatch.push_back(item);
         L.sb_end = (int32_t)an.sbatch.size() / 2;
-        if (L.sb_end - L.sb_begin - 1 > kSolveMaxBatches) return SLU_ERR_LIMIT;
     }
 
     // compact coupled triangles for the panel solves: sizes and the

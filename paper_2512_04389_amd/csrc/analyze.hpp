@@ -147,7 +147,6 @@ constexpr int kSsssmSmallM = 1200;
 // LDS staging of the triangular solves: items (panel rows) and chunks per batch.
 constexpr int kSolveItems = 512;
 constexpr int kSolveBatchChunks = 64;
-constexpr int kSolveMaxBatches = 256;
 constexpr int kSolveCont = 1 << 8;   // solve chunk continuing the previous one's coupled rows
 // Largest diagonal block factored in one LDS-resident chunk.
 constexpr int kLdsDenseMax = 128;

@@ -1667,9 +1667,8 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
     int *rowb = (int *)(Pn + kSolveItems * kPnLd);           // block row of every item
     int *icw = rowb + kSolveItems;                           // c0 << 5 | w of every item
     int *desc = icw + kSolveItems;                           // (c0, w, nr, item) per chunk
-    int *brec = desc + 4 * kSolveBatchChunks;                // batch records of the level
+    const int32_t *__restrict__ brec = sbatch + 2 * (size_t)L.sb_begin;   // batch records of the level
     const int nb = L.sb_end - L.sb_begin - 1;
-    for (int q = tid; q < 2 * (nb + 1); q += 256) brec[q] = sbatch[2 * (size_t)L.sb_begin + q];
     for (int e0 = tid; e0 < b * nc; e0 += 256 * 8) {
         double v[8];
 #pragma unroll
@@ -1801,7 +1800,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const double *__restrict__ s
 
 size_t solve_diag_lds_bytes(int max_b, int nc) {
     return ((((size_t)max_b * nc + 1) & ~(size_t)1) + (size_t)kSolveItems * kPnLd) * sizeof(double) +
-           (size_t)(2 * kSolveItems + 4 * kSolveBatchChunks + 2 * (kSolveMaxBatches + 1)) * sizeof(int);
+           (size_t)(2 * kSolveItems + 4 * kSolveBatchChunks) * sizeof(int);
 }
 
 hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,

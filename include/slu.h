@@ -258,6 +258,22 @@ int slu_set_getrf_split(slu_handle *h, double min_work);
  * graph is released and recaptured.  SLU_ERR_ARG for a negative min_rows. */
 int slu_set_getrf_tiled(slu_handle *h, int min_rows);
 
+/* Tile edge of the tiled GETRF: 32 (the default; four waves per tile, the
+ * step's 32 x 32 diagonal block factored as 2 x 2 blocks of 16) or 16 (one
+ * wave per tile).  Same factors up to rounding; a captured graph is
+ * recaptured.  SLU_ERR_ARG for another value. */
+int slu_set_getrf_tile(slu_handle *h, int tile);
+
+/* Blocked panel solves (Algorithm 1's GESSM / TSTRF, the panels of block
+ * column i times the inverse of the coupled triangle of L_ii or U_ii): with
+ * enable = 1 (the default), levels whose coupled triangles have at least 256
+ * columns solve their panels in 128-column blocks across the GPU (the
+ * blocks' inverted diagonal triangles, then one launch per block of
+ * right-looking updates on FP64 MFMA); 0 keeps the tile-by-tile solve, one
+ * workgroup per 16 or 32 panel rows, on every level.  Same results up to
+ * rounding.  A captured graph is recaptured.  SLU_ERR_ARG unless 0 or 1. */
+int slu_set_panel_blocked(slu_handle *h, int enable);
+
 /* Factorization precision.  SLU_PRECISION_FP64: every step in FP64.
  * SLU_PRECISION_FP32: the Schur updates (Algorithm 1's SSSSM, nearly all of
  * the flops) take their operands rounded to FP32 and accumulate in FP32 on

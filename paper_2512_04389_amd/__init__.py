@@ -250,6 +250,15 @@ class SparseLU:
         take the tiled GETRF (see ``slu_set_getrf_tiled``; 0: none)."""
         check(lib.slu_set_getrf_tiled(self._h, int(min_rows)), "slu_set_getrf_tiled")
 
+    def set_panel_blocked(self, enable=True):
+        """Blocked panel solves for wide coupled triangles (see
+        ``slu_set_panel_blocked``)."""
+        check(lib.slu_set_panel_blocked(self._h, 1 if enable else 0), "slu_set_panel_blocked")
+
+    def set_getrf_tile(self, tile):
+        """Tile edge of the tiled GETRF, 16 or 32 (see ``slu_set_getrf_tile``)."""
+        check(lib.slu_set_getrf_tile(self._h, int(tile)), "slu_set_getrf_tile")
+
     def set_precision(self, precision):
         """``"fp64"`` (default) or ``"fp32"`` (Schur updates in FP32 on the
         matrix cores, see ``slu_set_precision``) for later factorizations."""

@@ -640,6 +640,13 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                     if (tr / 16 != tc / 16) keys.push_back((int64_t)(tc / 16) * nt + tr / 16);
                 }
             }
+            if (kp >= kPanelBlkKp && L.m > 0) {
+                // blocked panel solve: it reads every upper tile of the
+                // coupled triangles, so the gather writes all of them
+                keys.clear();
+                for (int32_t row = 0; row < nt; ++row)
+                    for (int32_t col = row + 1; col < nt; ++col) keys.push_back((int64_t)row * nt + col);
+            }
             std::sort(keys.begin(), keys.end());
             keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
             size_t q = 0;
@@ -650,6 +657,23 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             an.trow_ptr.push_back((int32_t)an.trow_idx.size());
         }
         an.tri_doubles = toff;
+    }
+
+    // inverses of the kPanelBlk-column diagonal blocks of the coupled
+    // triangles, for the levels that take the blocked panel solve
+    {
+        int64_t boff = 0;
+        for (int64_t i = 0; i < p; ++i) {
+            LevelDev &L = an.levels[i];
+            if (L.kp >= kPanelBlkKp && L.m > 0) {
+                const int64_t nbk = (L.kp + kPanelBlk - 1) / kPanelBlk;
+                L.offB = boff;
+                boff += 2 * nbk * kPanelBlk * kPanelBlk;
+            } else {
+                L.offB = -1;
+            }
+        }
+        an.binv_doubles = boff;
     }
 
     // tiled GETRF work region (levels of more than one 16-row tile)

@@ -34,6 +34,7 @@ struct LevelDev {
     int64_t offD, offP, offQ;   // slab offsets in doubles
     int64_t offT;               // tri region offset in doubles
     int64_t offW;               // tiled GETRF work region offset in doubles (-1: none)
+    int64_t offB;               // blocked panel solve: inverted diagonal blocks (-1: none)
     int64_t Koff, Roff;         // offsets into K_idx / R_idx
     int64_t task_begin, task_end;   // segment pairs (SSSSM targets) in stgt, sa-major
     int64_t moff;                   // SSSSM offset tables in maps
@@ -128,6 +129,7 @@ struct Analysis {
     std::vector<int32_t> trow_idx;
     int64_t tri_doubles = 0;
     int64_t tgetrf_doubles = 0;      // tiled GETRF work region (panel copies, tile inverses)
+    int64_t binv_doubles = 0;        // blocked panel solve: inverted diagonal blocks
     std::vector<int64_t> slot;       // A entry (CSR order) -> slab position
     std::vector<int32_t> posK;       // global column -> position in K of its block, or -1
 
@@ -148,14 +150,20 @@ constexpr int kSsssmSmallM = 1200;
 constexpr int kSolveItems = 512;
 constexpr int kSolveBatchChunks = 64;
 constexpr int kSolveCont = 1 << 8;   // solve chunk continuing the previous one's coupled rows
+// Blocked panel solve: levels whose coupled triangles have at least
+// kPanelBlkKp columns solve their panels in column blocks of kPanelBlk with
+// the blocks' inverted diagonal triangles (chip-wide products).
+constexpr int kPanelBlk = 128;
+constexpr int kPanelBlkKp = 256;
 // Largest diagonal block factored in one LDS-resident chunk.
 constexpr int kLdsDenseMax = 128;
 // LDS budget of the chunked GETRF (bytes).
 constexpr int kGetrfLdsBudget = 150 * 1024;
-// Tiled GETRF: per level with b > 16 rows, two panel copies of 32 b doubles
-// (a tile column and a tile row of the diagonal block) and two pairs of
-// inverted 16 x 16 diagonal tiles.
-inline int64_t tgetrf_level_doubles(int32_t b) { return b > 16 ? 64 * (int64_t)b + 1024 : 0; }
+// Tiled GETRF: per level with b > 16 rows, two panel copies (a tile column
+// and a tile row of the diagonal block, 64 b doubles for 32-wide tiles) and
+// two pairs of inverted 32 x 32 diagonal tiles; the 16-wide tiles use the
+// first 64 b + 1024 doubles.
+inline int64_t tgetrf_level_doubles(int32_t b) { return b > 16 ? 128 * (int64_t)b + 4096 : 0; }
 
 // Returns SLU_OK or an SLU_ERR_* code; fills *out.
 // segments (optional): ascending row offsets 0 = s_0 < s_1 < ... < s_k = n of

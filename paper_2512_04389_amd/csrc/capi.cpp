@@ -16,7 +16,7 @@ struct slu_handle {
     void *ws = nullptr;
     slu::DevPlan dev{};
     // byte offsets of the workspace regions
-    size_t o_slab, o_tri, o_tgetrf, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
+    size_t o_slab, o_tri, o_tgetrf, o_binv, o_trow_ptr, o_trow_idx, o_levels, o_K, o_R, o_chunks, o_crows, o_schunks, o_sitems, o_sbatch, o_rseg, o_stgt, o_maps, o_slot, o_arow, o_acol,
         o_atcol, o_atrow, o_atv, o_perm, o_wlev, o_rlev, o_rtile, o_tsoff, o_info, o_scratch, o_ir, o_norms, o_vals;
     std::vector<int64_t> at_colptr;
     std::vector<int32_t> at_rowidx;
@@ -42,6 +42,8 @@ struct slu_handle {
     // waves whose largest diagonal block has at least this many rows take
     // the tiled GETRF (0: none)
     int getrf_tiled_rows = 1;
+    int getrf_tile = 32;        // tile edge of the tiled GETRF (16 or 32)
+    bool panel_blocked = true;  // blocked panel solve for wide coupled triangles
 };
 
 namespace {
@@ -68,6 +70,7 @@ void plan_workspace(slu_handle *h) {
     h->o_slab = take((size_t)an.slab_doubles * 8);
     h->o_tri = take((size_t)an.tri_doubles * 8);
     h->o_tgetrf = take((size_t)an.tgetrf_doubles * 8);
+    h->o_binv = take((size_t)an.binv_doubles * 8);
     h->o_trow_ptr = take(an.trow_ptr.size() * 4);
     h->o_trow_idx = take(an.trow_idx.size() * 4);
     h->o_levels = take(an.levels.size() * sizeof(slu::LevelDev));
@@ -348,6 +351,7 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
     d.slab = (double *)(base + h->o_slab);
     d.tri = (double *)(base + h->o_tri);
     d.tgetrf = an.tgetrf_doubles > 0 ? (double *)(base + h->o_tgetrf) : nullptr;
+    d.binv = an.binv_doubles > 0 ? (double *)(base + h->o_binv) : nullptr;
     d.trow_ptr = (const int32_t *)(base + h->o_trow_ptr);
     d.trow_idx = (const int32_t *)(base + h->o_trow_idx);
     d.levels = (const slu::LevelDev *)(base + h->o_levels);
@@ -454,9 +458,16 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         const bool chunk_fits = w.lds_getrf <= 160 * 1024;
         if ((h->getrf_tiled_rows > 0 && w.max_b >= h->getrf_tiled_rows) || !chunk_fits) {
             if (nlev > 65535) return SLU_ERR_LIMIT;
-            const int max_nt = (w.max_b + 15) / 16;
-            for (int k = 0; k < max_nt; ++k)
-                SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
+            if (h->getrf_tile == 32) {
+                const int max_nt = (w.max_b + 31) / 32;
+                const slu::LevelDev *one = nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr;
+                for (int k = 0; k < max_nt; ++k)
+                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile32(d, lv, nlev, k, max_nt, one, s));
+            } else {
+                const int max_nt = (w.max_b + 15) / 16;
+                for (int k = 0; k < max_nt; ++k)
+                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
+            }
             goto getrf_done;
         }
         {
@@ -495,7 +506,10 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     getrf_done:
         if (w.max_m > 0 && w.max_kp > 0) {
             SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, s));
+            const bool blk = h->panel_blocked && w.max_kp >= slu::kPanelBlkKp;
+            SLU_TIMED(SLU_KERNEL_PANEL,
+                      slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, blk ? 1 : 0, s));
+            if (blk) SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_blk_wave(d, lv, nlev, w.max_m, w.max_kp, s));
         }
         for (int r = w.round_begin; r < w.round_end; ++r)
             SLU_TIMED(SLU_KERNEL_SSSSM,
@@ -619,6 +633,26 @@ int slu_set_getrf_split(slu_handle *h, double min_work) {
 int slu_set_getrf_tiled(slu_handle *h, int min_rows) {
     if (!h || min_rows < 0) return SLU_ERR_ARG;
     h->getrf_tiled_rows = min_rows;
+    if (h->gexec) {   // a captured graph holds the other launch sequence
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    return SLU_OK;
+}
+
+int slu_set_getrf_tile(slu_handle *h, int tile) {
+    if (!h || (tile != 16 && tile != 32)) return SLU_ERR_ARG;
+    h->getrf_tile = tile;
+    if (h->gexec) {   // a captured graph holds the other launch sequence
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    return SLU_OK;
+}
+
+int slu_set_panel_blocked(slu_handle *h, int enable) {
+    if (!h || (enable != 0 && enable != 1)) return SLU_ERR_ARG;
+    h->panel_blocked = enable != 0;
     if (h->gexec) {   // a captured graph holds the other launch sequence
         (void)hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;

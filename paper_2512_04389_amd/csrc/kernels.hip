@@ -883,6 +883,262 @@ hipError_t launch_getrf_tile(const DevPlan &d, const int32_t *lvl, int nlev, int
     return hipGetLastError();
 }
 
+// 16 x 16 product of two LDS operands (row-major, leading dimensions la and
+// lb) by one wave, in the MFMA result layout (lane li + 16 g holds
+// C(g + 4 r, li)), and its store (times sign) to a row-major LDS image.
+__device__ __forceinline__ double4_t mm16_lds(const double *A, int la, const double *B, int lb, int li, int g) {
+    double a[4], bb[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        a[kk] = A[li * la + 4 * kk + g];
+        bb[kk] = B[(4 * kk + g) * lb + li];
+    }
+    double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bb[kk], c, 0, 0, 0);
+    return c;
+}
+
+__device__ __forceinline__ void st16_lds(double *C, int lc, const double4_t &c, int li, int g, double sign) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(g + 4 * r) * lc + li] = sign * c[r];
+}
+
+// LU of a 16 x 16 block of the row-major LDS image T (leading dimension ld)
+// by one wave, with the inverses of both factors written to IL / IU at the
+// same place; returns the first bad pivot (16 if none).
+__device__ __forceinline__ int lu16inv_lds(double *T, double *IL, double *IU, int ld, int li, int g) {
+    double a[4], e[4], f[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        a[t] = T[li * ld + 4 * g + t];
+        e[t] = li == 4 * g + t ? 1.0 : 0.0;
+        f[t] = e[t];
+    }
+    int bad = 16;
+    lu16inv_step<0>(a, e, f, li, g, bad);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        T[li * ld + 4 * g + t] = a[t];
+        IL[li * ld + 4 * g + t] = e[t];
+        IU[li * ld + 4 * g + t] = f[t];
+    }
+    return bad;
+}
+
+// The tiled GETRF of k_getrf_tile with 32 x 32 tiles and one workgroup of
+// four waves per tile, wave (qi, qj) owning the 16 x 16 quadrant (qi, qj):
+// launch s updates every trailing tile with the 32-column panel p = s - 1,
+//     Lt = A(I, p) U_pp^{-1},   Ut = L_pp^{-1} A(p, J),   A(I, J) -= Lt Ut,
+// each wave forming its quadrants of Lt and Ut (K = 32) and taking the other
+// halves it needs from its neighbours through LDS.  Tile (s, s) is then
+// factored as 2 x 2 blocks of 16: LU of block 00 (with inverses), U01 and
+// L10 by products with them, block 11 updated and factored, and the
+// off-diagonal blocks of the 32 x 32 inverses,
+//     U^{-1}_01 = -U00^{-1} U01 U11^{-1},  L^{-1}_10 = -L11^{-1} L10 L00^{-1}.
+// A wave of a single level gets the level's record as an argument (one),
+// saving two dependent loads on the critical path.  Panel copies and
+// inverses live in the level's work region: two copies of 64 b doubles (tile
+// column b x 32, tile row 32 x b column-major), then two pairs of 32 x 32
+// inverses, all by step parity.
+constexpr int kT32Ld = 33;
+
+__global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                                      const int32_t *__restrict__ lvl, int s,
+                                                      double *__restrict__ work,
+                                                      unsigned long long *__restrict__ info, LevelDev one,
+                                                      int use_one) {
+    __shared__ double xch[2][4][4][64];   // [lt / ut][wave][r][lane]
+    __shared__ double T[32 * kT32Ld], IL[32 * kT32Ld], IU[32 * kT32Ld];
+    __shared__ double S1[16 * 17], S2[16 * 17];
+    const LevelDev L = use_one ? one : levels[lvl[blockIdx.y]];
+    const int b = L.b;
+    const int nt = (b + 31) >> 5;
+    if (s >= nt) return;
+    const int q = blockIdx.x;
+    int I, J;
+    if (s == 0) {
+        if (q >= 2 * nt - 1) return;
+        I = q < nt ? q : 0;
+        J = q < nt ? 0 : q - nt + 1;
+    } else {
+        const int m = nt - s;
+        if (q >= m * m) return;
+        I = s + q / m;
+        J = s + q - (q / m) * m;
+    }
+    double *__restrict__ D = slab + L.offD;
+    double *__restrict__ W = work + (L.offW >= 0 ? L.offW : 0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+    const int qi = wave >> 1, qj = wave & 1;
+    const int rI = 32 * I, cJ = 32 * J;
+    const int row0 = rI + 16 * qi, col0 = cJ + 16 * qj;
+    const bool colok = col0 + li < b;
+    double4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = row0 + g + 4 * r;
+        acc[r] = (colok && row < b) ? D[(size_t)(col0 + li) * b + row] : 0.0;
+    }
+    if (s >= 1) {
+        const int p = s - 1;
+        const double *__restrict__ Pc = W + (size_t)(p & 1) * 64 * b;   // tile column p, b x 32
+        const double *__restrict__ Pr = Pc + (size_t)32 * b;           // tile row p, 32 x b (ld 32)
+        const double *__restrict__ iLg = W + 128 * (size_t)b + (p & 1) * 2048;
+        const double *__restrict__ iUg = iLg + 1024;
+        const int rowq = row0 + li;
+        const bool rowok = rowq < b;
+        double4_t lt = {0.0, 0.0, 0.0, 0.0}, ut = {0.0, 0.0, 0.0, 0.0};
+        double xa[8], ya[8], xb[8], yb[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const int k = 4 * kk + g;
+            xa[kk] = iUg[k * 32 + 16 * qj + li];                           // iU(k, 16 qj + li)
+            ya[kk] = rowok ? Pc[(size_t)k * b + rowq] : 0.0;                 // A(I, p)(16 qi + li, k)
+            xb[kk] = iLg[(16 * qi + li) * 32 + k];                         // iL(16 qi + li, k)
+            yb[kk] = colok ? Pr[(size_t)(col0 + li) * 32 + k] : 0.0;         // A(p, J)(k, 16 qj + li)
+        }
+        // lt(r) = Lt(16 qi + li, 16 qj + g + 4 r); ut(r) = Ut(16 qi + g + 4 r, 16 qj + li)
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            lt = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk], ya[kk], lt, 0, 0, 0);
+            ut = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[kk], yb[kk], ut, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            xch[0][wave][r][lane] = lt[r];
+            xch[1][wave][r][lane] = ut[r];
+        }
+        __syncthreads();
+        // quadrant (qi, qj) -= Lt(qi, h) Ut(h, qj), h = 0, 1 (waves 2 qi + h
+        // and 2 h + qj hold them, in operand layout)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int wl = 2 * qi + h, wu = 2 * h + qj;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-xch[0][wl][kk][lane], xch[1][wu][kk][lane], acc, 0, 0,
+                                                           0);
+        }
+        if (J == s && rowok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[(size_t)(32 * p + 16 * qj + g + 4 * r) * b + rowq] = lt[r];
+        }
+        if (I == s && colok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[(size_t)(col0 + li) * b + 32 * p + 16 * qi + g + 4 * r] = ut[r];
+        }
+    }
+    if (I != s || J != s) {
+        if (J == s) {   // next panel, tile column: its copy only
+            double *__restrict__ Pc = W + (size_t)(s & 1) * 64 * b;
+            if (colok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = row0 + g + 4 * r;
+                    if (row < b) Pc[(size_t)(16 * qj + li) * b + row] = acc[r];
+                }
+            }
+        } else if (I == s) {   // next panel, tile row
+            double *__restrict__ Pr = W + (size_t)(s & 1) * 64 * b + (size_t)32 * b;
+            if (colok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Pr[(size_t)(col0 + li) * 32 + 16 * qi + g + 4 * r] = acc[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + g + 4 * r;
+                if (colok && row < b) D[(size_t)(col0 + li) * b + row] = acc[r];
+            }
+        }
+        return;
+    }
+    // tile (s, s): rows / columns past b are an identity
+    const int w = min(32, b - rI);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * qi + g + 4 * r, col = 16 * qj + li;
+        double v = acc[r];
+        if (row >= w || col >= w) v = row == col ? 1.0 : 0.0;
+        T[row * kT32Ld + col] = v;
+    }
+    __syncthreads();
+    int bad = 32;
+    if (wave == 0) {
+        const int b0 = lu16inv_lds(T, IL, IU, kT32Ld, li, g);
+        if (b0 < 16) bad = b0;
+    }
+    __syncthreads();
+    if (wave == 1) {   // U01 = L00^{-1} A01
+        const double4_t c = mm16_lds(IL, kT32Ld, T + 16, kT32Ld, li, g);
+        st16_lds(T + 16, kT32Ld, c, li, g, 1.0);
+    } else if (wave == 2) {   // L10 = A10 U00^{-1}
+        const double4_t c = mm16_lds(T + 16 * kT32Ld, kT32Ld, IU, kT32Ld, li, g);
+        st16_lds(T + 16 * kT32Ld, kT32Ld, c, li, g, 1.0);
+    }
+    __syncthreads();
+    if (wave == 3) {   // A11 -= L10 U01, then its LU
+        double *A11 = T + 16 * kT32Ld + 16;
+        double4_t c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = A11[(g + 4 * r) * kT32Ld + li];
+        double a[4], bb[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            a[kk] = -T[(16 + li) * kT32Ld + 4 * kk + g];
+            bb[kk] = T[(4 * kk + g) * kT32Ld + 16 + li];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bb[kk], c, 0, 0, 0);
+        st16_lds(A11, kT32Ld, c, li, g, 1.0);
+        const int b1 = lu16inv_lds(A11, IL + 16 * kT32Ld + 16, IU + 16 * kT32Ld + 16, kT32Ld, li, g);
+        if (b1 < 16) bad = 16 + b1;
+    }
+    __syncthreads();
+    if (wave == 0) {   // U^{-1}_01 = -U00^{-1} U01 U11^{-1}
+        const double4_t c = mm16_lds(IU, kT32Ld, T + 16, kT32Ld, li, g);
+        st16_lds(S1, 17, c, li, g, 1.0);
+        const double4_t c2 = mm16_lds(S1, 17, IU + 16 * kT32Ld + 16, kT32Ld, li, g);
+        st16_lds(IU + 16, kT32Ld, c2, li, g, -1.0);
+    } else if (wave == 1) {   // L^{-1}_10 = -L11^{-1} L10 L00^{-1}
+        const double4_t c = mm16_lds(T + 16 * kT32Ld, kT32Ld, IL, kT32Ld, li, g);
+        st16_lds(S2, 17, c, li, g, 1.0);
+        const double4_t c2 = mm16_lds(IL + 16 * kT32Ld + 16, kT32Ld, S2, 17, li, g);
+        st16_lds(IL + 16 * kT32Ld, kT32Ld, c2, li, g, -1.0);
+    } else if (wave == 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            IU[(16 + g + 4 * r) * kT32Ld + li] = 0.0;
+            IL[(g + 4 * r) * kT32Ld + 16 + li] = 0.0;
+        }
+    }
+    if (lane == 0 && bad < w) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
+    __syncthreads();
+    double *__restrict__ iLw = W + 128 * (size_t)b + (s & 1) * 2048;
+    const bool more = s + 1 < nt;
+    for (int e = tid; e < 1024; e += 256) {
+        const int row = e >> 5, col = e & 31;
+        if (row < w && col < w) D[(size_t)(rI + col) * b + rI + row] = T[row * kT32Ld + col];
+        if (more) {
+            iLw[e] = IL[row * kT32Ld + col];
+            iLw[1024 + e] = IU[row * kT32Ld + col];
+        }
+    }
+}
+
+hipError_t launch_getrf_tile32(const DevPlan &d, const int32_t *lvl, int nlev, int s, int max_nt,
+                               const LevelDev *one, hipStream_t st) {
+    if (nlev <= 0 || s >= max_nt) return hipSuccess;
+    const int m = max_nt - s;
+    const unsigned gx = s == 0 ? (unsigned)(2 * max_nt - 1) : (unsigned)(m * m);
+    const int use_one = (nlev == 1 && one) ? 1 : 0;
+    const LevelDev arg = use_one ? *one : LevelDev{};
+    hipLaunchKernelGGL(k_getrf_tile32, dim3(gx, (unsigned)nlev), dim3(256), 0, st, d.slab, d.levels, lvl, s,
+                       d.tgetrf, d.info, arg, use_one);
+    return hipGetLastError();
+}
+
 // ------------------------------------------- compact coupled triangles
 // One workgroup per 16 x 16 tile that the panel solves read, numbered over
 // the wave's levels (soff: first workgroup of each level): per level the nt
@@ -988,11 +1244,11 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
                                                      const LevelDev *__restrict__ levels,
                                                      const int32_t *__restrict__ lvl,
                                                      const int32_t *__restrict__ trow_ptr,
-                                                     const int32_t *__restrict__ trow_idx) {
+                                                     const int32_t *__restrict__ trow_idx, int skip_blocked) {
     extern __shared__ double xs_lds[];
     const LevelDev L = levels[lvl[blockIdx.z]];
     const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
-    if (kp == 0 || (int)blockIdx.x * RT >= m) return;
+    if (kp == 0 || (int)blockIdx.x * RT >= m || (skip_blocked && L.offB >= 0)) return;
     const int panel = blockIdx.y;
     double *__restrict__ X = slab + (panel == 0 ? L.offP : L.offQ);
     const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
@@ -1098,11 +1354,11 @@ __global__ __launch_bounds__(256) void k_panel_solve_pf(double *__restrict__ sla
                                                      const LevelDev *__restrict__ levels,
                                                      const int32_t *__restrict__ lvl,
                                                      const int32_t *__restrict__ trow_ptr,
-                                                     const int32_t *__restrict__ trow_idx) {
+                                                     const int32_t *__restrict__ trow_idx, int skip_blocked) {
     extern __shared__ double xs_lds[];
     const LevelDev L = levels[lvl[blockIdx.z]];
     const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
-    if (kp == 0 || (int)blockIdx.x * RT >= m) return;
+    if (kp == 0 || (int)blockIdx.x * RT >= m || (skip_blocked && L.offB >= 0)) return;
     const int panel = blockIdx.y;
     double *__restrict__ X = slab + (panel == 0 ? L.offP : L.offQ);
     const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
@@ -1256,13 +1512,235 @@ __global__ __launch_bounds__(256) void k_panel_solve_pf(double *__restrict__ sla
     }
 }
 
+// ------------------------------------------------- blocked panel solves
+// For levels with wide coupled triangles (kp >= kPanelBlkKp) the panel solves
+// X <- X T^{-1} (X = P_i with T = Tu, X = Qt_i with T = Tl, both upper) run
+// in column blocks of kPanelBlk = 128 across the whole GPU:
+//   k_tri_binv: the inverse of every 128 x 128 diagonal block of T, one wave
+//     per 16-column tile j of a block: X_jj is the inverted 16 x 16 tile,
+//     X_ij = -T_ii^{-1} sum_{k = i+1..j} T_ik X_kj for i = j-1 .. 0;
+//   k_panel_blk, one launch per block step J: every workgroup takes 32 panel
+//     rows and one column block C > J and subtracts X(:, J) T(J, C) (the
+//     right-looking update with the solved block J); the workgroups of block
+//     C = J + 1 then multiply their rows by T_CC^{-1}, which solves block
+//     J + 1.  Launch J = -1 solves block 0.  No launch writes a block that
+//     another of its workgroups reads.
+// Every product is an FP64 MFMA 16 x 16 x 4 chain; the same X T^{-1} as the
+// tile-by-tile solve, with the substitutions grouped into block inverses.
+__global__ __launch_bounds__(64) void k_tri_binv(const double *__restrict__ tri, double *__restrict__ binv,
+                                                 const LevelDev *__restrict__ levels,
+                                                 const int32_t *__restrict__ lvl) {
+    const LevelDev L = levels[lvl[blockIdx.y]];
+    if (L.offB < 0) return;
+    const int kp = L.kp, nt = kp >> 4, nbk = (kp + kPanelBlk - 1) / kPanelBlk;
+    const int jb = blockIdx.x >> 3, j = blockIdx.x & 7;
+    if (jb >= nbk) return;
+    const int t0 = jb * 8, nbt = min(8, nt - t0);
+    if (j >= nbt) return;
+    const int panel = blockIdx.z;
+    const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
+    const double *__restrict__ Iv = tri + L.offT + 2 * (size_t)kp * kp + (size_t)panel * nt * 256;
+    double *__restrict__ out = binv + L.offB + ((size_t)panel * nbk + jb) * kPanelBlk * kPanelBlk;
+    const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+    // X[k] = tile (k, j) of the block inverse in the MFMA result layout,
+    // which is also the B-operand layout of a product with it
+    double4_t X[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) X[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k == j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[k][r] = Iv[(size_t)(t0 + k) * 256 + (g + 4 * r) * 16 + li];
+        }
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+        if (i >= j) continue;
+        double4_t S = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k <= i || k > j) continue;
+            double a[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                a[kk] = T[(size_t)(16 * (t0 + i) + li) * kp + 16 * (t0 + k) + 4 * kk + g];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) S = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], X[k][kk], S, 0, 0, 0);
+        }
+        double a[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) a[kk] = -Iv[(size_t)(t0 + i) * 256 + li * 16 + 4 * kk + g];
+        double4_t Y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) Y = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], S[kk], Y, 0, 0, 0);
+        X[i] = Y;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= nbt) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[(size_t)(16 * k + g + 4 * r) * kPanelBlk + 16 * j + li] = k <= j ? X[k][r] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_panel_blk(double *__restrict__ slab, const double *__restrict__ tri,
+                                                   const double *__restrict__ binv,
+                                                   const LevelDev *__restrict__ levels,
+                                                   const int32_t *__restrict__ lvl, int J, int rtiles_max) {
+    __shared__ double xs[32 * (kPanelBlk + 1)];
+    const LevelDev L = levels[lvl[blockIdx.y]];
+    if (L.offB < 0) return;
+    const int kp = L.kp, m = L.m, nbk = (kp + kPanelBlk - 1) / kPanelBlk;
+    const int rt = blockIdx.x % rtiles_max, cb = blockIdx.x / rtiles_max;
+    const int C = J + 1 + cb;
+    if (32 * rt >= m || C >= nbk) return;
+    const int panel = blockIdx.z;
+    double *__restrict__ X = slab + (panel == 0 ? L.offP : L.offQ);
+    const double *__restrict__ T = tri + L.offT + (size_t)panel * kp * kp;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+    const int r0 = 32 * rt, c0 = kPanelBlk * C, wb = min(kPanelBlk, kp - c0);
+    // the wave's output: rows r0 + 16 h + (g + 4 r), columns cw + 16 t + li
+    const int cw = c0 + 32 * wave;
+    const bool wact = 32 * wave < wb;
+    double4_t acc[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = cw + 16 * t + li;
+            const bool cok = wact && col < c0 + wb;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 16 * h + g + 4 * r;
+                acc[h][t][r] = (cok && row < m) ? X[(size_t)col * m + row] : 0.0;
+            }
+        }
+    if (J >= 0 && wact) {
+        // K = 128 in four batches of eight 4-deep steps; the loads of the
+        // next batch are in flight while the current one's MFMAs run
+        const int k0 = kPanelBlk * J;
+        const bool rok0 = r0 + li < m, rok1 = r0 + 16 + li < m;
+        const bool cok0 = cw + li < c0 + wb, cok1 = cw + 16 + li < c0 + wb;
+        constexpr int KB = 8, NB = kPanelBlk / 4 / KB;
+        double ca[2][KB][2], cbv[2][KB][2];
+        auto fetch = [&](int nb, double (&a)[KB][2], double (&bv)[KB][2]) {
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const int k = k0 + 4 * (nb * KB + u) + g;
+                a[u][0] = rok0 ? X[(size_t)k * m + r0 + li] : 0.0;
+                a[u][1] = rok1 ? X[(size_t)k * m + r0 + 16 + li] : 0.0;
+                bv[u][0] = cok0 ? T[(size_t)k * kp + cw + li] : 0.0;
+                bv[u][1] = cok1 ? T[(size_t)k * kp + cw + 16 + li] : 0.0;
+            }
+        };
+        fetch(0, ca[0], cbv[0]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            if (nb + 1 < NB) fetch(nb + 1, ca[(nb + 1) & 1], cbv[(nb + 1) & 1]);
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const double a0 = ca[nb & 1][u][0], a1 = ca[nb & 1][u][1];
+                const double b0 = cbv[nb & 1][u][0], b1 = cbv[nb & 1][u][1];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+    }
+    if (cb == 0) {
+        // block C = J + 1 is now final up to its own triangle: times T_CC^{-1}
+        constexpr int LD = kPanelBlk + 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xs[(16 * h + g + 4 * r) * LD + 32 * wave + 16 * t + li] = acc[h][t][r];
+        __syncthreads();
+        const double *__restrict__ Bi = binv + L.offB + ((size_t)panel * nbk + C) * kPanelBlk * kPanelBlk;
+        double4_t out[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) out[h][t] = double4_t{0.0, 0.0, 0.0, 0.0};
+        if (wact) {
+            // wb / 4 steps (a multiple of 4) in batches of four, the inverse's
+            // loads of the next batch in flight during the current MFMAs
+            const int nk = wb >> 2;
+            const bool bo0 = 32 * wave + li < wb, bo1 = 32 * wave + 16 + li < wb;
+            double bq[2][4][2];
+            auto fetchb = [&](int kb, double (&bv)[4][2]) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * (4 * kb + u) + g;
+                    bv[u][0] = bo0 ? Bi[(size_t)k * kPanelBlk + 32 * wave + li] : 0.0;
+                    bv[u][1] = bo1 ? Bi[(size_t)k * kPanelBlk + 32 * wave + 16 + li] : 0.0;
+                }
+            };
+            const int nkb = nk >> 2;
+            fetchb(0, bq[0]);
+            for (int kb = 0; kb < nkb; ++kb) {
+                if (kb + 1 < nkb) fetchb(kb + 1, bq[(kb + 1) & 1]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * (4 * kb + u) + g;
+                    const double a0 = xs[li * LD + k], a1 = xs[(16 + li) * LD + k];
+                    const double b0 = bq[kb & 1][u][0], b1 = bq[kb & 1][u][1];
+                    out[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, out[0][0], 0, 0, 0);
+                    out[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, out[0][1], 0, 0, 0);
+                    out[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, out[1][0], 0, 0, 0);
+                    out[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, out[1][1], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) acc[h][t] = out[h][t];
+    }
+    if (!wact) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = cw + 16 * t + li;
+            if (col >= c0 + wb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 16 * h + g + 4 * r;
+                if (row < m) X[(size_t)col * m + row] = acc[h][t][r];
+            }
+        }
+}
+
+hipError_t launch_panel_blk_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
+                                 hipStream_t s) {
+    if (nlev <= 0 || max_m <= 0 || max_kp < kPanelBlkKp) return hipSuccess;
+    const int nbk = (max_kp + kPanelBlk - 1) / kPanelBlk;
+    hipLaunchKernelGGL(k_tri_binv, dim3((unsigned)(8 * nbk), (unsigned)nlev, 2), dim3(64), 0, s, d.tri, d.binv,
+                       d.levels, lvl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rt = (max_m + 31) / 32;
+    for (int J = -1; J + 1 < nbk; ++J) {
+        const int ncb = J < 0 ? 1 : nbk - (J + 1);
+        hipLaunchKernelGGL(k_panel_blk, dim3((unsigned)(rt * ncb), (unsigned)nlev, 2), dim3(256), 0, s, d.slab,
+                           d.tri, d.binv, d.levels, lvl, J, rt);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Waves of at most kPanelPfLevels levels take the prefetching variant; waves
 // of many small levels (batches) the plain one, whose workgroups are
 // lighter (measured: 26 us against 60 us per launch on such waves).
 constexpr int kPanelPfLevels = 8;
 
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
-                                   hipStream_t s) {
+                                   int skip_blocked, hipStream_t s) {
     if (max_m <= 0 || max_kp <= 0) return hipSuccess;
     if (nlev <= kPanelPfLevels) {
         const size_t tab = panel_tables_bytes(max_kp);
@@ -1271,13 +1749,13 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
         if (lds32 <= 150 * 1024) {
             dim3 grid((unsigned)((max_m + 31) / 32), 2, (unsigned)nlev);
             hipLaunchKernelGGL((k_panel_solve_pf<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, lvl,
-                               d.trow_ptr, d.trow_idx);
+                               d.trow_ptr, d.trow_idx, skip_blocked);
             return hipGetLastError();
         }
         if (lds16 <= 150 * 1024) {
             dim3 grid((unsigned)((max_m + 15) / 16), 2, (unsigned)nlev);
             hipLaunchKernelGGL((k_panel_solve_pf<16, true>), grid, dim3(256), lds16, s, d.slab, d.tri, d.levels, lvl,
-                               d.trow_ptr, d.trow_idx);
+                               d.trow_ptr, d.trow_idx, skip_blocked);
             return hipGetLastError();
         }
     }
@@ -1285,15 +1763,15 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
     if (lds32 <= 150 * 1024) {
         dim3 grid((unsigned)((max_m + 31) / 32), 2, (unsigned)nlev);
         hipLaunchKernelGGL((k_panel_solve<32, true>), grid, dim3(256), lds32, s, d.slab, d.tri, d.levels, lvl,
-                           d.trow_ptr, d.trow_idx);
+                           d.trow_ptr, d.trow_idx, skip_blocked);
     } else if (lds16 <= 150 * 1024) {
         dim3 grid((unsigned)((max_m + 15) / 16), 2, (unsigned)nlev);
         hipLaunchKernelGGL((k_panel_solve<16, true>), grid, dim3(256), lds16, s, d.slab, d.tri, d.levels, lvl,
-                           d.trow_ptr, d.trow_idx);
+                           d.trow_ptr, d.trow_idx, skip_blocked);
     } else {
         dim3 grid((unsigned)((max_m + 15) / 16), 2, (unsigned)nlev);
         hipLaunchKernelGGL((k_panel_solve<16, false>), grid, dim3(256), 0, s, d.slab, d.tri, d.levels, lvl,
-                           d.trow_ptr, d.trow_idx);
+                           d.trow_ptr, d.trow_idx, skip_blocked);
     }
     return hipGetLastError();
 }

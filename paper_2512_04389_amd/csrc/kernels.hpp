@@ -14,6 +14,7 @@ struct DevPlan {
     double *slab;
     double *tri;                // compact coupled triangles (see LevelDev)
     double *tgetrf;             // tiled GETRF panel copies and inverted tiles (LevelDev.offW)
+    double *binv;               // blocked panel solve: inverted diagonal blocks (LevelDev.offB)
     const int32_t *trow_ptr;
     const int32_t *trow_idx;
     const LevelDev *levels;
@@ -72,11 +73,20 @@ hipError_t launch_getrf_trail(const DevPlan &d, const int32_t *lvl, int nlev, in
 // Tiled GETRF of a wave, tile step s (0 <= s < max_nt, the largest number of
 // 16-row tiles of the wave's diagonal blocks).
 hipError_t launch_getrf_tile(const DevPlan &d, const int32_t *lvl, int nlev, int s, int max_nt, hipStream_t st);
+// The same with 32 x 32 tiles (max_nt in 32-row tiles); one: the host copy
+// of the level's record when the wave has a single level (else null).
+hipError_t launch_getrf_tile32(const DevPlan &d, const int32_t *lvl, int nlev, int s, int max_nt,
+                               const LevelDev *one, hipStream_t st);
 // soff: first workgroup of each of the wave's levels; slots: their total.
 hipError_t launch_tri_gather_wave(const DevPlan &d, const int32_t *lvl, const int32_t *soff, int nlev, int slots,
                                   hipStream_t s);
+// skip_blocked: leave out the levels that take the blocked panel solve.
 hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
-                                   hipStream_t s);
+                                   int skip_blocked, hipStream_t s);
+// Blocked panel solve of the wave's levels with kp >= kPanelBlkKp: the
+// inverted diagonal blocks, then one launch per column block.
+hipError_t launch_panel_blk_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
+                                 hipStream_t s);
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s);
 
 // Solve pieces on the permuted work block W (n x nc, leading dimension n).

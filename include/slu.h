@@ -308,10 +308,11 @@ int slu_get_info(const slu_handle *h, slu_info *info);
 #define SLU_NUM_KERNELS 4
 
 /* Enable (1) or disable (0) per-kernel timing.  While enabled, slu_factor
- * records a HIP event pair on its stream around every kernel launch and
- * adds the elapsed times per kernel class; slu_get_kernel_times reports the
- * totals of the last slu_factor.  Timing adds host-side event work between
- * launches; it does not change results. */
+ * records a HIP event pair on its stream around every run of consecutive
+ * launches of one kernel class (a wave's GETRF steps, its panel solves, its
+ * Schur-update rounds) and adds the elapsed times and launch counts per
+ * class; slu_get_kernel_times reports the totals of the last slu_factor.
+ * Timing adds event work between the runs; it does not change results. */
 int slu_set_profiling(slu_handle *h, int enable);
 /* ms[SLU_NUM_KERNELS]: summed kernel milliseconds of the last factor;
  * launches[SLU_NUM_KERNELS]: launch counts. */

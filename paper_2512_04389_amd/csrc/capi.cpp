@@ -24,6 +24,7 @@ struct slu_handle {
     bool profiling = false;
     std::vector<hipEvent_t> ev;          // event pool for per-kernel timing
     std::vector<int> ev_kind;            // kernel class of each recorded pair
+    std::vector<int64_t> ev_count;       // launches inside each recorded pair
     double kern_ms[SLU_NUM_KERNELS] = {0, 0, 0, 0};
     int64_t kern_n[SLU_NUM_KERNELS] = {0, 0, 0, 0};
     bool bound = false;
@@ -394,7 +395,10 @@ int slu_bind_workspace(slu_handle *h, void *device_ptr, size_t bytes, void *stre
 }
 
 namespace {
-// Per-kernel timing: an event pair around a launch when profiling is on.
+// Per-kernel timing when profiling is on: an event pair around each run of
+// consecutive launches of one kernel class (a wave's GETRF steps, its panel
+// solves, its Schur-update rounds), with the number of launches inside, so
+// the events add little to the launch sequence they time.
 struct KernelTimer {
     slu_handle *h;
     hipStream_t s;
@@ -409,9 +413,16 @@ struct KernelTimer {
                 h->ev.push_back(e);
             }
         }
-        if (h->ev_kind.size() < h->ev.size() / 2) h->ev_kind.resize(h->ev.size() / 2);
+        if (h->ev_kind.size() < h->ev.size() / 2) {
+            h->ev_kind.resize(h->ev.size() / 2);
+            h->ev_count.resize(h->ev.size() / 2);
+        }
         h->ev_kind[used / 2] = kind;
+        h->ev_count[used / 2] = 0;
         return hipEventRecord(h->ev[used], s);
+    }
+    void launched(int count = 1) {
+        if (h->profiling) h->ev_count[used / 2] += count;
     }
     hipError_t end() {
         if (!h->profiling) return hipSuccess;
@@ -430,7 +441,7 @@ struct KernelTimer {
             hipError_t e = hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]);
             if (hip_failed(e)) return e;
             h->kern_ms[h->ev_kind[q / 2]] += ms;
-            h->kern_n[h->ev_kind[q / 2]] += 1;
+            h->kern_n[h->ev_kind[q / 2]] += h->ev_count[q / 2];
         }
         return hipSuccess;
     }
@@ -441,18 +452,28 @@ struct KernelTimer {
 static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, KernelTimer &kt) {
     const slu::Analysis &an = h->an;
     const slu::DevPlan &d = h->dev;
-#define SLU_TIMED(kind, call)                                              \
+#define SLU_BEGIN(kind)                                                    \
     do {                                                                   \
         if (hip_failed(kt.begin(kind))) return SLU_ERR_HIP;              \
+    } while (0)
+#define SLU_LAUNCH(call)                                                   \
+    do {                                                                   \
         if (hip_failed((call))) return SLU_ERR_HIP;                      \
+        kt.launched();                                                     \
+    } while (0)
+#define SLU_END()                                                          \
+    do {                                                                   \
         if (hip_failed(kt.end())) return SLU_ERR_HIP;                    \
     } while (0)
     if (hip_failed(slu::launch_info_reset(d, s))) return SLU_ERR_HIP;
-    SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_zero(d.slab, an.slab_doubles, s));
-    SLU_TIMED(SLU_KERNEL_SCATTER, slu::launch_scatter(d, values, s));
+    SLU_BEGIN(SLU_KERNEL_SCATTER);
+    SLU_LAUNCH(slu::launch_zero(d.slab, an.slab_doubles, s));
+    SLU_LAUNCH(slu::launch_scatter(d, values, s));
+    SLU_END();
     for (const slu::WaveInfo &w : an.waves) {
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
+        SLU_BEGIN(SLU_KERNEL_GETRF);
         // the tiled GETRF when selected, and for waves whose chunked GETRF
         // would not fit the LDS
         const bool chunk_fits = w.lds_getrf <= 160 * 1024;
@@ -461,12 +482,10 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
             if (h->getrf_tile == 32) {
                 const int max_nt = (w.max_b + 31) / 32;
                 const slu::LevelDev *one = nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr;
-                for (int k = 0; k < max_nt; ++k)
-                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile32(d, lv, nlev, k, max_nt, one, s));
+                for (int k = 0; k < max_nt; ++k) SLU_LAUNCH(slu::launch_getrf_tile32(d, lv, nlev, k, max_nt, one, s));
             } else {
                 const int max_nt = (w.max_b + 15) / 16;
-                for (int k = 0; k < max_nt; ++k)
-                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
+                for (int k = 0; k < max_nt; ++k) SLU_LAUNCH(slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
             }
             goto getrf_done;
         }
@@ -487,10 +506,10 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
             }
         }
         if (!split) {
-            SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
+            SLU_LAUNCH(slu::launch_getrf_wave(d, lv, nlev, w.lds_getrf, s));
         } else {
             for (int k = 0; k < nsteps; ++k) {
-                SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_step(d, lv, nlev, k, w.lds_getrf, s));
+                SLU_LAUNCH(slu::launch_getrf_step(d, lv, nlev, k, w.lds_getrf, s));
                 int max_tiles = 0;
                 for (int q = w.begin; q < w.end; ++q) {
                     const slu::LevelDev &L = an.levels[an.wave_levels[q]];
@@ -498,24 +517,33 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
                     const int ntl = (an.chunks[L.chunk_begin + k].nr + 15) / 16;
                     max_tiles = std::max(max_tiles, ntl * ntl);
                 }
-                if (max_tiles > 0)
-                    SLU_TIMED(SLU_KERNEL_GETRF, slu::launch_getrf_trail(d, lv, nlev, k, max_tiles, s));
+                if (max_tiles > 0) SLU_LAUNCH(slu::launch_getrf_trail(d, lv, nlev, k, max_tiles, s));
             }
         }
         }
     getrf_done:
+        SLU_END();
         if (w.max_m > 0 && w.max_kp > 0) {
-            SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
+            SLU_BEGIN(SLU_KERNEL_PANEL);
+            SLU_LAUNCH(slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             const bool blk = h->panel_blocked && w.max_kp >= slu::kPanelBlkKp;
-            SLU_TIMED(SLU_KERNEL_PANEL,
-                      slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, blk ? 1 : 0, s));
-            if (blk) SLU_TIMED(SLU_KERNEL_PANEL, slu::launch_panel_blk_wave(d, lv, nlev, w.max_m, w.max_kp, s));
+            SLU_LAUNCH(slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, blk ? 1 : 0, s));
+            if (blk) {
+                if (hip_failed(slu::launch_panel_blk_wave(d, lv, nlev, w.max_m, w.max_kp, s))) return SLU_ERR_HIP;
+                kt.launched(1 + (w.max_kp + slu::kPanelBlk - 1) / slu::kPanelBlk);
+            }
+            SLU_END();
         }
-        for (int r = w.round_begin; r < w.round_end; ++r)
-            SLU_TIMED(SLU_KERNEL_SSSSM,
-                      slu::launch_ssssm_round(d, an.rounds[r], h->precision == SLU_PRECISION_FP32, s));
+        if (w.round_end > w.round_begin) {
+            SLU_BEGIN(SLU_KERNEL_SSSSM);
+            for (int r = w.round_begin; r < w.round_end; ++r)
+                SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], h->precision == SLU_PRECISION_FP32, s));
+            SLU_END();
+        }
     }
-#undef SLU_TIMED
+#undef SLU_BEGIN
+#undef SLU_LAUNCH
+#undef SLU_END
     return SLU_OK;
 }
 

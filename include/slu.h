@@ -264,6 +264,16 @@ int slu_set_getrf_tiled(slu_handle *h, int min_rows);
  * recaptured.  SLU_ERR_ARG for another value. */
 int slu_set_getrf_tile(slu_handle *h, int tile);
 
+/* Tiled diagonal solves: in slu_solve, slu_solve_transpose and the solves
+ * inside slu_solve_refined, a wave whose largest diagonal block has at least
+ * min_rows rows (default 256; 0: never), whose blocks are dense (S fills at
+ * least half of every block's lower triangle) and were factored by the
+ * 32 x 32 tiled GETRF solves its diagonal blocks tile by tile across the GPU
+ * with the inverted diagonal tiles the factorization kept (one launch per
+ * tile step; one workgroup per block otherwise).  Same results up to
+ * rounding.  SLU_ERR_ARG for a negative min_rows. */
+int slu_set_solve_tiled(slu_handle *h, int min_rows);
+
 /* Blocked panel solves (Algorithm 1's GESSM / TSTRF, the panels of block
  * column i times the inverse of the coupled triangle of L_ii or U_ii): with
  * enable = 1 (the default), levels whose coupled triangles have at least 256

@@ -255,6 +255,11 @@ class SparseLU:
         ``slu_set_panel_blocked``)."""
         check(lib.slu_set_panel_blocked(self._h, 1 if enable else 0), "slu_set_panel_blocked")
 
+    def set_solve_tiled(self, min_rows):
+        """Tiled diagonal solves for waves with blocks of at least ``min_rows``
+        rows (see ``slu_set_solve_tiled``; 0: never)."""
+        check(lib.slu_set_solve_tiled(self._h, int(min_rows)), "slu_set_solve_tiled")
+
     def set_getrf_tile(self, tile):
         """Tile edge of the tiled GETRF, 16 or 32 (see ``slu_set_getrf_tile``)."""
         check(lib.slu_set_getrf_tile(self._h, int(tile)), "slu_set_getrf_tile")

@@ -812,6 +812,19 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 w.max_kp = std::max(w.max_kp, L.kp);
                 w.max_m = std::max(w.max_m, L.m);
                 w.max_b = std::max(w.max_b, L.b);
+                w.min_b = w.min_b == 0 ? L.b : std::min(w.min_b, L.b);
+                if (L.b > 32) {
+                    // share of the block's lower triangle that S fills
+                    int64_t in = 0;
+                    const int64_t r0 = L.r0, r1 = (int64_t)L.r0 + L.b;
+                    for (int64_t c = r0; c < r1; ++c) {
+                        const int32_t *lo = an.s_rowidx.data() + an.s_colptr[c];
+                        const int32_t *hi = an.s_rowidx.data() + an.s_colptr[c + 1];
+                        in += std::lower_bound(lo, hi, (int32_t)r1) - lo;
+                    }
+                    const int32_t pct = (int32_t)(100 * in / ((int64_t)L.b * (L.b + 1) / 2));
+                    w.min_dense_pct = std::min(w.min_dense_pct, pct);
+                }
                 if (L.b <= kLdsDenseMax) w.any_dense = 1; else w.any_chunked = 1;
             }
             w.end = (int32_t)an.wave_levels.size();

@@ -76,6 +76,8 @@ struct WaveInfo {
     int32_t max_kp;             // largest kp
     int32_t any_dense, any_chunked;
     int32_t max_b;              // largest diagonal block
+    int32_t min_b;              // smallest diagonal block
+    int32_t min_dense_pct = 100; // least share (%) of a block's lower triangle in S, blocks of 33+ rows
     int32_t round_begin, round_end;
 };
 
@@ -161,9 +163,12 @@ constexpr int kLdsDenseMax = 128;
 constexpr int kGetrfLdsBudget = 150 * 1024;
 // Tiled GETRF: per level with b > 16 rows, two panel copies (a tile column
 // and a tile row of the diagonal block, 64 b doubles for 32-wide tiles) and
-// two pairs of inverted 32 x 32 diagonal tiles; the 16-wide tiles use the
-// first 64 b + 1024 doubles.
-inline int64_t tgetrf_level_doubles(int32_t b) { return b > 16 ? 128 * (int64_t)b + 4096 : 0; }
+// the inverted L and U of every 32 x 32 diagonal tile (2048 doubles per
+// tile, kept for the tiled solves); the 16-wide tiles use the first
+// 64 b + 1024 doubles.
+inline int64_t tgetrf_level_doubles(int32_t b) {
+    return b > 16 ? 128 * (int64_t)b + 2048 * (int64_t)((b + 31) / 32) : 0;
+}
 
 // Returns SLU_OK or an SLU_ERR_* code; fills *out.
 // segments (optional): ascending row offsets 0 = s_0 < s_1 < ... < s_k = n of

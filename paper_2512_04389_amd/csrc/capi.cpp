@@ -45,6 +45,12 @@ struct slu_handle {
     int getrf_tiled_rows = 1;
     int getrf_tile = 32;        // tile edge of the tiled GETRF (16 or 32)
     bool panel_blocked = true;  // blocked panel solve for wide coupled triangles
+    // diagonal solves of waves whose largest block has at least this many
+    // rows use the tiled solve when their blocks were factored by the 32 x 32
+    // tiled GETRF (0: never); wave_tinv: per wave, the last factor kept the
+    // inverted diagonal tiles
+    int solve_tiled_rows = 256;
+    std::vector<char> wave_tinv;
 };
 
 namespace {
@@ -127,6 +133,18 @@ hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s
     return hipMemcpyAsync((char *)base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// The diagonal solves of wave wi take the tiled solve: its blocks were
+// factored by the 32 x 32 tiled GETRF (the inverted diagonal tiles are kept),
+// every block has a tiled work region, the wave's largest block reaches the
+// threshold and its blocks are dense (at least half of every block's lower
+// triangle in S: the one-workgroup solve walks only the coupled rows of
+// sparse blocks and wins there).
+bool tiled_solve(const slu_handle *h, size_t wi) {
+    const slu::WaveInfo &w = h->an.waves[wi];
+    return h->solve_tiled_rows > 0 && wi < h->wave_tinv.size() && h->wave_tinv[wi] && w.min_b > 16 &&
+           w.max_b >= h->solve_tiled_rows && w.min_dense_pct >= 50 && w.end - w.begin <= 65535;
+}
+
 int solve_check(const slu_handle *h, const double *B, const double *X, int64_t nrhs, int64_t ld) {
     if (!h || (!B && nrhs > 0) || (!X && nrhs > 0) || nrhs < 0) return SLU_ERR_ARG;
     if (!h->bound) return SLU_ERR_STATE;
@@ -150,10 +168,16 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
         // row takes its updates in round order, so the sums are
         // deterministic); the backward sweep mirrors it, with the updates of
         // a whole wave together (each level writes only its own block)
-        for (const slu::WaveInfo &w : an.waves) {
+        for (size_t wi = 0; wi < an.waves.size(); ++wi) {
+            const slu::WaveInfo &w = an.waves[wi];
             const int nlev = w.end - w.begin;
-            if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
+            if (tiled_solve(h, wi)) {
+                if (hip_failed(slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
+                    return SLU_ERR_HIP;
+            } else if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans,
+                                                              s))) {
                 return SLU_ERR_HIP;
+            }
             for (int r = w.round_begin; r < w.round_end; ++r) {
                 const slu::RoundInfo &ri = an.rounds[r];
                 int max_m = 0;
@@ -173,8 +197,14 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
             }
             if (hip_failed(slu::launch_bwd_update(d, d.wave_levels + w.begin, nlev, max_kappa, nc, trans, s)))
                 return SLU_ERR_HIP;
-            if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
+            if (tiled_solve(h, wi)) {
+                if (hip_failed(
+                        slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
+                    return SLU_ERR_HIP;
+            } else if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc,
+                                                              trans, s))) {
                 return SLU_ERR_HIP;
+            }
         }
         e = slu::launch_scatter_perm(d, X + c0 * ld, ld, nc, s);
         if (hip_failed(e)) return SLU_ERR_HIP;
@@ -470,7 +500,9 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     SLU_LAUNCH(slu::launch_zero(d.slab, an.slab_doubles, s));
     SLU_LAUNCH(slu::launch_scatter(d, values, s));
     SLU_END();
-    for (const slu::WaveInfo &w : an.waves) {
+    h->wave_tinv.assign(an.waves.size(), 0);
+    for (size_t wi = 0; wi < an.waves.size(); ++wi) {
+        const slu::WaveInfo &w = an.waves[wi];
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
         SLU_BEGIN(SLU_KERNEL_GETRF);
@@ -483,6 +515,7 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
                 const int max_nt = (w.max_b + 31) / 32;
                 const slu::LevelDev *one = nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr;
                 for (int k = 0; k < max_nt; ++k) SLU_LAUNCH(slu::launch_getrf_tile32(d, lv, nlev, k, max_nt, one, s));
+                h->wave_tinv[wi] = 1;
             } else {
                 const int max_nt = (w.max_b + 15) / 16;
                 for (int k = 0; k < max_nt; ++k) SLU_LAUNCH(slu::launch_getrf_tile(d, lv, nlev, k, max_nt, s));
@@ -685,6 +718,12 @@ int slu_set_panel_blocked(slu_handle *h, int enable) {
         (void)hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;
     }
+    return SLU_OK;
+}
+
+int slu_set_solve_tiled(slu_handle *h, int min_rows) {
+    if (!h || min_rows < 0) return SLU_ERR_ARG;
+    h->solve_tiled_rows = min_rows;
     return SLU_OK;
 }
 

@@ -938,9 +938,9 @@ __device__ __forceinline__ int lu16inv_lds(double *T, double *IL, double *IU, in
 //     U^{-1}_01 = -U00^{-1} U01 U11^{-1},  L^{-1}_10 = -L11^{-1} L10 L00^{-1}.
 // A wave of a single level gets the level's record as an argument (one),
 // saving two dependent loads on the critical path.  Panel copies and
-// inverses live in the level's work region: two copies of 64 b doubles (tile
-// column b x 32, tile row 32 x b column-major), then two pairs of 32 x 32
-// inverses, all by step parity.
+// inverses live in the level's work region: two copies of 64 b doubles by
+// step parity (tile column b x 32, tile row 32 x b column-major), then the
+// 32 x 32 inverses of L and U of every diagonal tile (kept for the solves).
 constexpr int kT32Ld = 33;
 
 __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab, const LevelDev *__restrict__ levels,
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         const int p = s - 1;
         const double *__restrict__ Pc = W + (size_t)(p & 1) * 64 * b;   // tile column p, b x 32
         const double *__restrict__ Pr = Pc + (size_t)32 * b;           // tile row p, 32 x b (ld 32)
-        const double *__restrict__ iLg = W + 128 * (size_t)b + (p & 1) * 2048;
+        const double *__restrict__ iLg = W + 128 * (size_t)b + (size_t)p * 2048;
         const double *__restrict__ iUg = iLg + 1024;
         const int rowq = row0 + li;
         const bool rowok = rowq < b;
@@ -1115,12 +1115,14 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
     }
     if (lane == 0 && bad < w) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
     __syncthreads();
-    double *__restrict__ iLw = W + 128 * (size_t)b + (s & 1) * 2048;
-    const bool more = s + 1 < nt;
+    // every tile's inverses are kept (slot s): the next step reads them, and
+    // so do the tiled triangular solves after the factorization
+    const bool keep = L.offW >= 0;
+    double *__restrict__ iLw = W + 128 * (size_t)b + (size_t)s * 2048;
     for (int e = tid; e < 1024; e += 256) {
         const int row = e >> 5, col = e & 31;
         if (row < w && col < w) D[(size_t)(rI + col) * b + rI + row] = T[row * kT32Ld + col];
-        if (more) {
+        if (keep) {
             iLw[e] = IL[row * kT32Ld + col];
             iLw[1024 + e] = IU[row * kT32Ld + col];
         }
@@ -2291,6 +2293,140 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
         hipLaunchKernelGGL(k_solve_diag<false>, dim3((unsigned)nlev), dim3(256), lds, s, d.slab, d.levels, lvl,
                            d.schunks, d.sitems, d.sbatch, d.scratch, d.n, nc, trans);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ tiled diagonal solves
+// Diagonal-block solves of a wave whose blocks were factored by the 32 x 32
+// tiled GETRF, with the inverted diagonal tiles it kept: for the forward
+// sweep (L, or U^T when transposed) tile t gives x_t = M_t b_t and every
+// later row tile r takes b_r -= A_rt x_t; the backward sweep (U, or L^T)
+// runs the same from the last tile up.  One launch per tile step u = 0..nt,
+// one wave per (level, row tile r): it finalizes x of the tile solved in
+// step u - 1 when r is that tile (nobody reads it in step u), and otherwise
+// forms x of tile u itself from b_u (read-only in step u) and updates its
+// own rows.  M_t is iL_t, iU_t^T, iU_t or iL_t^T; A_rt is the block's tile
+// (r, t), transposed for the transposed solve.  The right-hand sides of a
+// 32-row tile are the 16 columns of 16 x 16 x 4 FP64 MFMA products (nc <= 16).
+__global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ slab, const double *__restrict__ work,
+                                                   const LevelDev *__restrict__ levels,
+                                                   const int32_t *__restrict__ lvl, int u, int fwd, int trans,
+                                                   double *__restrict__ Wx, int64_t n, int nc) {
+    const LevelDev L = levels[lvl[blockIdx.y]];
+    const int b = L.b, nt = (b + 31) >> 5;
+    if (u > nt) return;
+    const int q = blockIdx.x;
+    // step u handles tile t (solved now) and finalizes tile tp (solved in u - 1)
+    const int t = fwd ? u : nt - 1 - u;
+    const int tp = fwd ? u - 1 : nt - u;
+    // workgroup q: the finalized tile first (q = 0, when u > 0), then the
+    // tiles that tile t updates, walking away from t
+    int r;
+    const int q0 = u > 0 ? 1 : 0;
+    if (u > 0 && q == 0)
+        r = tp;
+    else
+        r = fwd ? t + 1 + (q - q0) : t - 1 - (q - q0);
+    if (r < 0 || r >= nt) return;
+    const double *__restrict__ D = slab + L.offD;
+    const double *__restrict__ Inv = work + L.offW + 128 * (size_t)b;
+    const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+    const bool rhs_ok = li < nc;
+    double *__restrict__ Xc = Wx + (size_t)(rhs_ok ? li : 0) * n + L.r0;   // this lane's right-hand side
+    const bool use_l = (fwd != 0) == (trans == 0);   // M and A from L (else from U)
+    // M_s (row-major 32 x 32 inverses of tile s): element (i, k) of the
+    // operator applied, i.e. iL / iU, transposed for the transposed solve
+    auto mload = [&](int s2, int i, int k) -> double {
+        const double *Mb = Inv + (size_t)s2 * 2048 + (use_l ? 0 : 1024);
+        return trans ? Mb[k * 32 + i] : Mb[i * 32 + k];
+    };
+    // x of tile s2 (32 rows) = M b_s2 in result layout: half h, lane (li, g),
+    // element r -> row 16 h + g + 4 r, right-hand side li
+    auto solve_tile = [&](int s2, double4_t (&x)[2]) {
+        double bb[2][4];
+#pragma unroll
+        for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int row = 32 * s2 + 16 * hk + 4 * kk + g;
+                bb[hk][kk] = (rhs_ok && row < b) ? Xc[row] : 0.0;
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            x[h] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double a = mload(s2, 16 * h + li, 16 * hk + 4 * kk + g);
+                    x[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[hk][kk], x[h], 0, 0, 0);
+                }
+        }
+    };
+    if (u > 0 && r == tp) {
+        double4_t x[2];
+        solve_tile(tp, x);
+        if (rhs_ok) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 32 * tp + 16 * h + g + 4 * e;
+                    if (row < b) Xc[row] = x[h][e];
+                }
+        }
+        return;
+    }
+    if (u >= nt) return;
+    double4_t x[2];
+    solve_tile(t, x);
+    // b_r -= A_rt x_t: A_rt(i, k) = D(32 r + i, 32 t + k), or D(32 t + k, 32 r + i)
+    // for the transposed solve
+    double4_t acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 32 * r + 16 * h + g + 4 * e;
+            acc[h][e] = (rhs_ok && row < b) ? Xc[row] : 0.0;
+        }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ri = 32 * r + 16 * h + li;
+#pragma unroll
+        for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int ck = 32 * t + 16 * hk + 4 * kk + g;
+                double a = 0.0;
+                if (ri < b && ck < b) a = trans ? D[(size_t)ri * b + ck] : D[(size_t)ck * b + ri];
+                acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, x[hk][kk], acc[h], 0, 0, 0);
+            }
+    }
+    if (rhs_ok) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 32 * r + 16 * h + g + 4 * e;
+                if (row < b) Xc[row] = acc[h][e];
+            }
+    }
+}
+
+hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
+                                  int trans, hipStream_t s) {
+    if (nlev <= 0 || nlev > 65535) return hipErrorInvalidValue;
+    const int nt = (max_b + 31) / 32;
+    for (int u = 0; u <= nt; ++u) {
+        // rows handled in step u: the finalized tile plus the tiles it updates
+        const unsigned gx = (unsigned)(u == 0 ? nt - 1 : (nt - u > 1 ? nt - u : 1));
+        if (gx == 0) continue;
+        hipLaunchKernelGGL(k_solve_tile, dim3(gx, (unsigned)nlev), dim3(64), 0, s, d.slab, d.tgetrf, d.levels, lvl,
+                           u, fwd ? 1 : 0, trans, d.scratch, d.n, nc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // W[rows_i[a]] -= X[a, :] . W[r0 + K_i]   (X = P_i, or Qt_i when transposed)

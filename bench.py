@@ -256,7 +256,7 @@ def solve_block(W, nrhs, torch):
     return torch.from_numpy(np.ascontiguousarray(b)).cuda(), xt
 
 
-def regular_sweep(W, vals, B, sizes, steps, torch):
+def regular_sweep(W, vals, B, sizes, steps, torch, tune):
     import numpy as np
     out = []
     for bs in sizes:
@@ -266,6 +266,8 @@ def regular_sweep(W, vals, B, sizes, steps, torch):
         hr = make_handle(W, blocking="regular", block_size=bs)
         an_s = time.perf_counter() - t0
         hr.bind()
+        if tune and bs <= 1000:
+            hr.autotune(vals, reps=1)
         rms, _ = time_factor(hr, vals, steps, 1, torch)
         X = hr.solve(B)
         eta = float(np.max(hr.backward_error(vals, B, X)))
@@ -291,6 +293,11 @@ def measure(W, args, torch, full):
     F = info["flops"]
     log("analyzed in %.2f s: levels %d, waves %d, nnz(S) %d, F %.4g" %
         (analyze_s, info["nblocks"], info["waves"], info["nnz_s"], F))
+    # the library's autotuner picks the launch shapes for this matrix; the
+    # timed factors run with its choice
+    tune = h.autotune(vals, reps=2) if args.autotune else None
+    if tune:
+        log("autotune: %s" % ", ".join("%.1f ms" % r["ms"] for r in tune))
     steps = args.steps if full else max(3, args.steps // 2)
     ms, wall_ms = time_factor(h, vals, steps, args.warmup, torch)
     singles = sorted(time_once(lambda: h.factor(vals), torch)[0] for _ in range(max(5, steps)))
@@ -298,7 +305,7 @@ def measure(W, args, torch, full):
            "levels": info["nblocks"], "waves": info["waves"], "rounds": info["rounds"],
            "nonempty_blocks": info["nonempty_blocks"], "ms": ms, "wall_ms": wall_ms,
            "median_ms": singles[len(singles) // 2], "min_ms": singles[0], "gflops": F / (ms * 1e-3) / 1e9,
-           "analyze_s": analyze_s}
+           "analyze_s": analyze_s, "autotune": tune}
     B, xt = solve_block(W, W["nrhs"], torch)
     h.solve(B)
     solve_ms, X = time_once(lambda: h.solve(B), torch)
@@ -339,6 +346,8 @@ def measure(W, args, torch, full):
         gan = time.perf_counter() - t0
         gi = hg.info()
         hg.bind()
+        if args.autotune:
+            hg.autotune(vals, reps=1)
         gms, _ = time_factor(hg, vals, max(2, steps // 2), 1, torch)
         Xg = hg.solve(B)
         res["graph_nd"] = {"ms": gms, "gflops": gi["flops"] / (gms * 1e-3) / 1e9, "nnz_s": gi["nnz_s"],
@@ -349,7 +358,7 @@ def measure(W, args, torch, full):
         del hg
         torch.cuda.empty_cache()
     sizes = [int(x) for x in args.regular.split(",") if x] if full else [500]
-    res["regular"] = regular_sweep(W, vals, B, sizes, max(2, steps // 2), torch)
+    res["regular"] = regular_sweep(W, vals, B, sizes, max(2, steps // 2), torch, args.autotune)
     if res["regular"]:
         best = min(res["regular"], key=lambda r: r["ms"])
         res["regular_best"] = {"block": best["block"], "ms": best["ms"], "irregular_speedup": best["ms"] / ms}
@@ -393,6 +402,8 @@ def batch_measure(nsys, args, torch):
     vals = torch.from_numpy(np.concatenate([x[3] for x in sy])).cuda()
     F = info["flops"]
     steps = max(3, args.steps // 2)
+    tune = h.autotune(vals, reps=2) if args.autotune else None
+    h.set_graph(False)
     ms, _ = time_factor(h, vals, steps, args.warmup, torch)
     h.set_graph(True)
     ms_g, _ = time_factor(h, vals, steps, args.warmup, torch)
@@ -411,7 +422,7 @@ def batch_measure(nsys, args, torch):
                        "dissection" % nsys, "n_total": h.n, "nnz_s": info["nnz_s"], "flops": F,
            "levels": info["nblocks"], "waves": info["waves"], "rounds": info["rounds"], "analyze_s": analyze_s,
            "ms_launches": ms, "ms_graph": ms_g, "gflops": F / (min(ms, ms_g) * 1e-3) / 1e9,
-           "solve_ms": solve_ms, "eta": eta,
+           "solve_ms": solve_ms, "eta": eta, "autotune": tune,
            "fp32": {"ms": ms32, "gflops": F / (ms32 * 1e-3) / 1e9, "corrections": its,
                     "eta": float(np.max(eta_r)), "converged": bool(conv)}}
     h.close()
@@ -432,6 +443,8 @@ def main():
                     help="further workloads reported as extra keys (comma separated, empty: none)")
     ap.add_argument("--cpu-budget", type=float, default=1.5e10, help="oracle flops timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the library's default launch shapes instead of the autotuner's choice")
     ap.add_argument("--pmc-program", action="store_true", help="calibration copy + one factor (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the per-launch HBM traffic summary of --workload from two counter runs")
@@ -477,7 +490,7 @@ def main():
         "per_kernel": res["per_kernel_ms"], "roofline": roofline, "rooflines": rl,
         "regular": res["regular"], "regular_best": res.get("regular_best"), "graph_nd": res.get("graph_nd"),
         "fp32_ir": res["fp32_ir"],
-        "cpu_baseline": res.get("cpu_baseline"), "extra": extras,
+        "cpu_baseline": res.get("cpu_baseline"), "autotune": res.get("autotune"), "extra": extras,
     }
     print(json.dumps(line), flush=True)
 

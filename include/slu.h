@@ -264,6 +264,30 @@ int slu_set_getrf_tiled(slu_handle *h, int min_rows);
  * recaptured.  SLU_ERR_ARG for another value. */
 int slu_set_getrf_tile(slu_handle *h, int tile);
 
+/* One row of the autotuner's table: a launch-shape setting and its median
+ * factor time. */
+typedef struct {
+    int32_t getrf_tiled_rows;     /* slu_set_getrf_tiled                     */
+    int32_t getrf_tile;           /* slu_set_getrf_tile                      */
+    int32_t panel_blocked;        /* slu_set_panel_blocked                   */
+    int32_t graph;                /* slu_set_graph                           */
+    double ms;                    /* median of reps factors (HIP events)     */
+} slu_tune_entry;
+
+/* Autotuner of the launch shapes for this handle's pattern and values (the
+ * batch of independent systems included): factors with each of a fixed set
+ * of settings (tiled GETRF with 32- or 16-row tiles or the chunked GETRF,
+ * blocked or tile-wise panel solves, launch by launch or graph replay), one
+ * warm-up and reps timed factors each on `stream`, keeps the setting with the
+ * smallest median and factors once more with it, so the handle ends factored
+ * and set to the choice.  table (capacity entries, may be NULL when capacity
+ * is 0) receives the settings tried in order, *count (may be NULL) their
+ * number.  values: device float64[nnz_a] as in slu_factor.  Returns SLU_OK,
+ * SLU_ZERO_PIVOT, SLU_ERR_ARG (reps < 1, negative capacity, null pointers),
+ * SLU_ERR_STATE (no workspace) or SLU_ERR_HIP.  Synchronizes `stream`. */
+int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *table, int capacity, int *count,
+                 void *stream);
+
 /* Tiled diagonal solves: in slu_solve, slu_solve_transpose and the solves
  * inside slu_solve_refined, a wave whose largest diagonal block has at least
  * min_rows rows (default 256; 0: never), whose blocks are dense (S fills at

@@ -255,6 +255,25 @@ class SparseLU:
         ``slu_set_panel_blocked``)."""
         check(lib.slu_set_panel_blocked(self._h, 1 if enable else 0), "slu_set_panel_blocked")
 
+    def autotune(self, values, reps=2, stream=None):
+        """Try the library's launch-shape settings on these values and keep
+        the fastest (``slu_autotune``); returns the table of settings tried
+        with their median factor times, the chosen one first."""
+        _check_dev("values", values, self._bound(), numel=self._nnz())
+        cap = 16
+        table = (_abi.slu_tune_entry * cap)()
+        cnt = ctypes.c_int(0)
+        rc = lib.slu_autotune(self._h, _dptr(values), int(reps), ctypes.cast(table, ctypes.c_void_p), cap,
+                              ctypes.byref(cnt), _stream(stream))
+        if rc == _abi.SLU_ZERO_PIVOT:
+            raise ZeroPivot(self.info()["zero_pivot_col"])
+        check(rc, "slu_autotune")
+        self._serial += 1
+        rows = [{name: getattr(table[i], name) for name, _ in _abi.slu_tune_entry._fields_}
+                for i in range(min(cnt.value, cap))]
+        rows.sort(key=lambda r: r["ms"])
+        return rows
+
     def set_solve_tiled(self, min_rows):
         """Tiled diagonal solves for waves with blocks of at least ``min_rows``
         rows (see ``slu_set_solve_tiled``; 0: never)."""

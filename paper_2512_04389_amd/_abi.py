@@ -47,7 +47,7 @@ EXPORTS = [
     "slu_get_kernel_times", "slu_value_gradient", "slu_set_precision", "slu_solve_refined",
     "slu_analyze_batch", "slu_set_graph", "slu_last_hip_error", "slu_hip_error_string",
     "slu_set_host_threads", "slu_set_getrf_split", "slu_set_getrf_tiled", "slu_solve_noalloc", "slu_set_getrf_tile",
-    "slu_set_panel_blocked", "slu_set_solve_tiled",
+    "slu_set_panel_blocked", "slu_set_solve_tiled", "slu_autotune",
 ]
 
 
@@ -63,6 +63,16 @@ class slu_options(ctypes.Structure):
         ("grid_dims", ctypes.c_int32 * 3),
         ("schedule", ctypes.c_int32),
         ("user_perm", ctypes.c_void_p),
+    ]
+
+
+class slu_tune_entry(ctypes.Structure):
+    _fields_ = [
+        ("getrf_tiled_rows", ctypes.c_int32),
+        ("getrf_tile", ctypes.c_int32),
+        ("panel_blocked", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
+        ("ms", ctypes.c_double),
     ]
 
 
@@ -134,6 +144,7 @@ def _load():
         "slu_set_getrf_tile": (i32, [hp, ctypes.c_int]),
         "slu_set_panel_blocked": (i32, [hp, ctypes.c_int]),
         "slu_set_solve_tiled": (i32, [hp, ctypes.c_int]),
+        "slu_autotune": (i32, [hp, p, i32, p, i32, ctypes.POINTER(ctypes.c_int), p]),
         "slu_last_hip_error": (i32, []),
         "slu_set_host_threads": (i32, [i32]),
         "slu_hip_error_string": (ctypes.c_char_p, [i32]),

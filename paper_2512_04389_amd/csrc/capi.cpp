@@ -721,6 +721,78 @@ int slu_set_panel_blocked(slu_handle *h, int enable) {
     return SLU_OK;
 }
 
+int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *table, int capacity, int *count,
+                 void *stream) {
+    if (!h || (!values && h->an.nnz_a > 0) || reps < 1 || capacity < 0 || (capacity > 0 && !table)) return SLU_ERR_ARG;
+    if (!h->bound) return SLU_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    // the launch-shape settings tried: GETRF path x panel path x graph replay
+    struct Cfg {
+        int tiled_rows, tile, panel, graph;
+    };
+    const Cfg cfgs[] = {{1, 32, 1, 0}, {1, 32, 0, 0}, {1, 16, 1, 0}, {0, 32, 1, 0},
+                        {1, 32, 1, 1}, {1, 16, 1, 1}, {0, 32, 1, 1}};
+    const int ncfg = (int)(sizeof(cfgs) / sizeof(cfgs[0]));
+    const bool prof = h->profiling;
+    h->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SLU_OK;
+    if (hip_failed(hipEventCreate(&e0)) || hip_failed(hipEventCreate(&e1))) rc = SLU_ERR_HIP;
+    int best = -1;
+    double best_ms = 0.0;
+    int n = 0;
+    std::vector<float> t((size_t)reps);
+    for (int c = 0; c < ncfg && rc == SLU_OK; ++c) {
+        h->getrf_tiled_rows = cfgs[c].tiled_rows;
+        h->getrf_tile = cfgs[c].tile;
+        h->panel_blocked = cfgs[c].panel != 0;
+        if (h->gexec) {
+            (void)hipGraphExecDestroy(h->gexec);
+            h->gexec = nullptr;
+        }
+        h->use_graph = cfgs[c].graph != 0;
+        rc = slu_factor(h, values, stream);   // warm-up (and graph capture)
+        for (int r = 0; r < reps && rc == SLU_OK; ++r) {
+            if (hip_failed(hipEventRecord(e0, s))) rc = SLU_ERR_HIP;
+            if (rc == SLU_OK) rc = slu_factor(h, values, stream);
+            if (rc == SLU_OK && hip_failed(hipEventRecord(e1, s))) rc = SLU_ERR_HIP;
+            if (rc == SLU_OK && hip_failed(hipEventSynchronize(e1))) rc = SLU_ERR_HIP;
+            if (rc == SLU_OK && hip_failed(hipEventElapsedTime(&t[r], e0, e1))) rc = SLU_ERR_HIP;
+        }
+        if (rc != SLU_OK) break;
+        std::sort(t.begin(), t.end());
+        const double ms = t[(size_t)reps / 2];
+        if (n < capacity) {
+            table[n].getrf_tiled_rows = cfgs[c].tiled_rows;
+            table[n].getrf_tile = cfgs[c].tile;
+            table[n].panel_blocked = cfgs[c].panel;
+            table[n].graph = cfgs[c].graph;
+            table[n].ms = ms;
+        }
+        ++n;
+        if (best < 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (count) *count = n;
+    if (best >= 0) {
+        h->getrf_tiled_rows = cfgs[best].tiled_rows;
+        h->getrf_tile = cfgs[best].tile;
+        h->panel_blocked = cfgs[best].panel != 0;
+        if (h->gexec) {
+            (void)hipGraphExecDestroy(h->gexec);
+            h->gexec = nullptr;
+        }
+        h->use_graph = cfgs[best].graph != 0;
+        if (rc == SLU_OK) rc = slu_factor(h, values, stream);   // the handle ends factored with the choice
+    }
+    h->profiling = prof;
+    return rc;
+}
+
 int slu_set_solve_tiled(slu_handle *h, int min_rows) {
     if (!h || min_rows < 0) return SLU_ERR_ARG;
     h->solve_tiled_rows = min_rows;

@@ -30,6 +30,8 @@ def _dense_dd(n, seed):
 CASES = {
     "dense-900-regular-600": lambda: (_dense_dd(900, 5), dict(blocking="regular", block_size=600)),
     "dense-1100-regular-300": lambda: (_dense_dd(1100, 6), dict(blocking="regular", block_size=300)),
+    # panel rows above 2000 in the first levels
+    "dense-2600-regular-300": lambda: (_dense_dd(2600, 7), dict(blocking="regular", block_size=300)),
     "bbd-6000-regular-700": lambda: (synth.bbd_circuit(n=6000, nblocks=4, border=300, border_nnz=20000, seed=9),
                                      dict(blocking="regular", block_size=700)),
     "convdiff-16-regular-800": lambda: (synth.convection_diffusion_3d(16),

@@ -904,24 +904,55 @@ __device__ __forceinline__ void st16_lds(double *C, int lc, const double4_t &c, 
     for (int r = 0; r < 4; ++r) C[(g + 4 * r) * lc + li] = sign * c[r];
 }
 
-// LU of a 16 x 16 block of the row-major LDS image T (leading dimension ld)
-// by one wave, with the inverses of both factors written to IL / IU at the
-// same place; returns the first bad pivot (16 if none).
-__device__ __forceinline__ int lu16inv_lds(double *T, double *IL, double *IU, int ld, int li, int g) {
-    double a[4], e[4], f[4];
+// Pivot K of the no-pivot LU of a 16 x 16 block held by one wave in the
+// strided layout, lane i + 16 g holding a[s] = A(i, g + 4 s): the layout in
+// which an MFMA result C lands as C^T, so a product can feed the LU without
+// going through LDS.  The elimination's row operations are applied to e as
+// well (e starts as I and ends as L^{-1}).  With SCALE, every row of e is
+// finally divided by its pivot (the lane keeps its row's pivot reciprocal in
+// rrow), which gives D^{-1} L^{-1} for pivots D: run on A^T = U^T L^T, whose
+// unit lower factor is U^T D^{-1}, that is (U^{-1})^T.  Only the columns
+// that can change at step K are touched: a's columns right of K and e's
+// columns up to K (row K of e is zero right of K).  bad: the first zero or
+// non-finite pivot (16 if none).
+template <int K, bool SCALE>
+__device__ __forceinline__ void lu16s_step(double (&a)[4], double (&e)[4], int i, int g, int &bad,
+                                           double &rrow) {
+    constexpr int g0 = K & 3, s0 = K >> 2;
+    const double piv = bcast_lane(a[s0], K + 16 * g0);
+    if (!(piv != 0.0 && isfinite(piv))) bad = min(bad, K);
+    const double rp = recip(piv);
+    if constexpr (SCALE) rrow = i == K ? rp : rrow;
+    const double lg = i > K ? a[s0] * rp : 0.0;          // L(i, K) in column group g0
+    if (g == g0 && i > K) a[s0] = lg;
+    const double l = perm_lane(lg, i + 16 * g0);        // zero on rows <= K
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        a[t] = T[li * ld + 4 * g + t];
-        e[t] = li == 4 * g + t ? 1.0 : 0.0;
-        f[t] = e[t];
+    for (int s = 0; s < 4; ++s) {
+        if (4 * s + 3 > K) {                             // columns g + 4 s > K exist
+            double u = bcast16<K>(a[s]);                 // U(K, g + 4 s)
+            if (s == s0) u = g > g0 ? u : 0.0;
+            a[s] = a[s] - l * u;
+        }
+        if (4 * s <= K) {                                // columns g + 4 s <= K exist
+            const double ek = bcast16<K>(e[s]);
+            e[s] = e[s] - l * ek;
+        }
     }
-    int bad = 16;
-    lu16inv_step<0>(a, e, f, li, g, bad);
+    if constexpr (K + 1 < 16) lu16s_step<K + 1, SCALE>(a, e, i, g, bad, rrow);
+}
+
+// LU of the 16 x 16 block a (strided layout) with e = L^{-1}, or, with SCALE,
+// e = (U^{-1})^T of the block's transpose; returns the first bad pivot.
+template <bool SCALE>
+__device__ __forceinline__ int lu16s(double (&a)[4], double (&e)[4], int li, int g) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        T[li * ld + 4 * g + t] = a[t];
-        IL[li * ld + 4 * g + t] = e[t];
-        IU[li * ld + 4 * g + t] = f[t];
+    for (int t = 0; t < 4; ++t) e[t] = li == g + 4 * t ? 1.0 : 0.0;
+    int bad = 16;
+    double rrow = 1.0;
+    lu16s_step<0, SCALE>(a, e, li, g, bad, rrow);
+    if constexpr (SCALE) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) e[t] *= rrow;
     }
     return bad;
 }
@@ -932,26 +963,35 @@ __device__ __forceinline__ int lu16inv_lds(double *T, double *IL, double *IU, in
 //     Lt = A(I, p) U_pp^{-1},   Ut = L_pp^{-1} A(p, J),   A(I, J) -= Lt Ut,
 // each wave forming its quadrants of Lt and Ut (K = 32) and taking the other
 // halves it needs from its neighbours through LDS.  Tile (s, s) is then
-// factored as 2 x 2 blocks of 16: LU of block 00 (with inverses), U01 and
-// L10 by products with them, block 11 updated and factored, and the
-// off-diagonal blocks of the 32 x 32 inverses,
-//     U^{-1}_01 = -U00^{-1} U01 U11^{-1},  L^{-1}_10 = -L11^{-1} L10 L00^{-1}.
-// A wave of a single level gets the level's record as an argument (one),
-// saving two dependent loads on the critical path.  Panel copies and
-// inverses live in the level's work region: two copies of 64 b doubles by
-// step parity (tile column b x 32, tile row 32 x b column-major), then the
-// 32 x 32 inverses of L and U of every diagonal tile (kept for the solves).
+// factored as 2 x 2 blocks of 16 with the inverses of its factors:
+//   waves 0, 1: LU of block 00 with L00^{-1} (wave 0), and the same
+//               elimination of its transpose giving U00^{-T} (wave 1);
+//               U01 = L00^{-1} A01, L10 = A10 U00^{-1};
+//   waves 2, 3: A11 - L10 U01, formed by each in the layout its LU needs,
+//               LU with L11^{-1} (wave 2) and U11^{-T} (wave 3); meanwhile
+//               waves 0, 1 form U00^{-1} U01 and L10 L00^{-1};
+//   waves 2, 3: U^{-1}_01 = -U00^{-1} U01 U11^{-1}, L^{-1}_10 = -L11^{-1} L10 L00^{-1}.
+// Every result goes to global memory from the registers that hold it.  With
+// ONE the wave has a single level, whose record is the kernel argument one.
+// Panel copies and inverses live in the level's work region: two copies of
+// 64 b doubles by step parity (tile column b x 32, tile row 32 x b
+// column-major), then the 32 x 32 inverses of L and U (row-major) of every
+// diagonal tile (kept for the solves).
 constexpr int kT32Ld = 33;
 
+template <bool ONE>
 __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab, const LevelDev *__restrict__ levels,
                                                       const int32_t *__restrict__ lvl, int s,
                                                       double *__restrict__ work,
-                                                      unsigned long long *__restrict__ info, LevelDev one,
-                                                      int use_one) {
+                                                      unsigned long long *__restrict__ info, LevelDev one) {
     __shared__ double xch[2][4][4][64];   // [lt / ut][wave][r][lane]
-    __shared__ double T[32 * kT32Ld], IL[32 * kT32Ld], IU[32 * kT32Ld];
-    __shared__ double S1[16 * 17], S2[16 * 17];
-    const LevelDev L = use_one ? one : levels[lvl[blockIdx.y]];
+    __shared__ double T[32 * kT32Ld];
+    __shared__ double IL0[16 * 17], IU0[16 * 17], S1[16 * 17], S2[16 * 17];
+    LevelDev L;
+    if constexpr (ONE)
+        L = one;
+    else
+        L = levels[lvl[blockIdx.y]];
     const int b = L.b;
     const int nt = (b + 31) >> 5;
     if (s >= nt) return;
@@ -974,12 +1014,14 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
     const int rI = 32 * I, cJ = 32 * J;
     const int row0 = rI + 16 * qi, col0 = cJ + 16 * qj;
     const bool colok = col0 + li < b;
+    const size_t colc = (size_t)min(col0 + li, b - 1);
+    // every load below is issued unconditionally from a clamped address, so
+    // that they all go out together: rows and columns past b hold copies of
+    // in-range values, are never stored and never reach an in-range entry
+    // (the diagonal tile replaces them by the identity)
     double4_t acc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = row0 + g + 4 * r;
-        acc[r] = (colok && row < b) ? D[(size_t)(col0 + li) * b + row] : 0.0;
-    }
+    for (int r = 0; r < 4; ++r) acc[r] = D[colc * b + min(row0 + g + 4 * r, b - 1)];
     if (s >= 1) {
         const int p = s - 1;
         const double *__restrict__ Pc = W + (size_t)(p & 1) * 64 * b;   // tile column p, b x 32
@@ -988,15 +1030,16 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         const double *__restrict__ iUg = iLg + 1024;
         const int rowq = row0 + li;
         const bool rowok = rowq < b;
+        const int rowc = min(rowq, b - 1);
         double4_t lt = {0.0, 0.0, 0.0, 0.0}, ut = {0.0, 0.0, 0.0, 0.0};
         double xa[8], ya[8], xb[8], yb[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
             const int k = 4 * kk + g;
             xa[kk] = iUg[k * 32 + 16 * qj + li];                           // iU(k, 16 qj + li)
-            ya[kk] = rowok ? Pc[(size_t)k * b + rowq] : 0.0;                 // A(I, p)(16 qi + li, k)
+            ya[kk] = Pc[(size_t)k * b + rowc];                             // A(I, p)(16 qi + li, k)
             xb[kk] = iLg[(16 * qi + li) * 32 + k];                         // iL(16 qi + li, k)
-            yb[kk] = colok ? Pr[(size_t)(col0 + li) * 32 + k] : 0.0;         // A(p, J)(k, 16 qj + li)
+            yb[kk] = Pr[colc * 32 + k];                                    // A(p, J)(k, 16 qj + li)
         }
         // lt(r) = Lt(16 qi + li, 16 qj + g + 4 r); ut(r) = Ut(16 qi + g + 4 r, 16 qj + li)
 #pragma unroll
@@ -1064,67 +1107,113 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         T[row * kT32Ld + col] = v;
     }
     __syncthreads();
-    int bad = 32;
+    const bool keep = L.offW >= 0;
+    double *__restrict__ iLw = W + 128 * (size_t)b + (size_t)s * 2048;   // row-major 32 x 32
+    double *__restrict__ iUw = iLw + 1024;
+    double *__restrict__ Dt = D + (size_t)rI * b + rI;                   // the tile, column-major, ld b
+    double a[4], e[4];
     if (wave == 0) {
-        const int b0 = lu16inv_lds(T, IL, IU, kT32Ld, li, g);
-        if (b0 < 16) bad = b0;
-    }
-    __syncthreads();
-    if (wave == 1) {   // U01 = L00^{-1} A01
-        const double4_t c = mm16_lds(IL, kT32Ld, T + 16, kT32Ld, li, g);
+        // block 00: LU and L00^{-1}; U01 = L00^{-1} A01
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = T[li * kT32Ld + g + 4 * t];
+        const int bad = lu16s<false>(a, e, li, g);
+        if (lane == 0 && bad < min(16, w)) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
+        double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(e[kk], T[(g + 4 * kk) * kT32Ld + 16 + li], c, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = g + 4 * t;
+            IL0[li * 17 + col] = e[t];
+            if (li < w && col < w) Dt[(size_t)col * b + li] = a[t];
+            if (keep) {
+                iLw[li * 32 + col] = e[t];
+                iLw[(g + 4 * t) * 32 + 16 + li] = 0.0;                      // L^{-1}_01
+            }
+        }
         st16_lds(T + 16, kT32Ld, c, li, g, 1.0);
-    } else if (wave == 2) {   // L10 = A10 U00^{-1}
-        const double4_t c = mm16_lds(T + 16 * kT32Ld, kT32Ld, IU, kT32Ld, li, g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (g + 4 * r < w && 16 + li < w) Dt[(size_t)(16 + li) * b + g + 4 * r] = c[r];
+    } else if (wave == 1) {
+        // block 00 transposed: U00^{-T}; L10 = A10 U00^{-1}
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = T[(g + 4 * t) * kT32Ld + li];
+        (void)lu16s<true>(a, e, li, g);                                     // e(li, g + 4 t) = U00^{-1}(g + 4 t, li)
+        double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(T[(16 + li) * kT32Ld + g + 4 * kk], e[kk], c, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            IU0[(g + 4 * t) * 17 + li] = e[t];
+            if (keep) {
+                iUw[(g + 4 * t) * 32 + li] = e[t];
+                iUw[(16 + g + 4 * t) * 32 + li] = 0.0;                      // U^{-1}_10
+            }
+        }
         st16_lds(T + 16 * kT32Ld, kT32Ld, c, li, g, 1.0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (16 + g + 4 * r < w && li < w) Dt[(size_t)li * b + 16 + g + 4 * r] = c[r];
     }
     __syncthreads();
-    if (wave == 3) {   // A11 -= L10 U01, then its LU
-        double *A11 = T + 16 * kT32Ld + 16;
+    if (wave >= 2) {
+        // A11 - L10 U01: wave 2 forms its transpose (the strided layout of
+        // the block), wave 3 the block itself (the strided layout of its
+        // transpose)
+        const bool tr = wave == 2;
         double4_t c;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] = A11[(g + 4 * r) * kT32Ld + li];
-        double a[4], bb[4];
+        for (int r = 0; r < 4; ++r)
+            c[r] = tr ? T[(16 + li) * kT32Ld + 16 + g + 4 * r] : T[(16 + g + 4 * r) * kT32Ld + 16 + li];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            a[kk] = -T[(16 + li) * kT32Ld + 4 * kk + g];
-            bb[kk] = T[(4 * kk + g) * kT32Ld + 16 + li];
+            const double u01 = T[(g + 4 * kk) * kT32Ld + 16 + li];         // U01(g + 4 kk, li)
+            const double l10 = T[(16 + li) * kT32Ld + g + 4 * kk];         // L10(li, g + 4 kk)
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(tr ? -u01 : -l10, tr ? l10 : u01, c, 0, 0, 0);
         }
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bb[kk], c, 0, 0, 0);
-        st16_lds(A11, kT32Ld, c, li, g, 1.0);
-        const int b1 = lu16inv_lds(A11, IL + 16 * kT32Ld + 16, IU + 16 * kT32Ld + 16, kT32Ld, li, g);
-        if (b1 < 16) bad = 16 + b1;
-    }
-    __syncthreads();
-    if (wave == 0) {   // U^{-1}_01 = -U00^{-1} U01 U11^{-1}
-        const double4_t c = mm16_lds(IU, kT32Ld, T + 16, kT32Ld, li, g);
+        for (int t = 0; t < 4; ++t) a[t] = c[t];
+        if (tr) {
+            const int bad = lu16s<false>(a, e, li, g);
+            if (lane == 0 && bad < w - 16) atomicMin(info, (unsigned long long)(L.r0 + rI + 16 + bad));
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int col = 16 + g + 4 * t;
+                if (16 + li < w && col < w) Dt[(size_t)col * b + 16 + li] = a[t];
+                if (keep) iLw[(16 + li) * 32 + col] = e[t];
+            }
+        } else {
+            (void)lu16s<true>(a, e, li, g);
+            if (keep) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) iUw[(16 + g + 4 * t) * 32 + 16 + li] = e[t];
+            }
+        }
+    } else if (wave == 0) {   // U00^{-1} U01
+        const double4_t c = mm16_lds(IU0, 17, T + 16, kT32Ld, li, g);
         st16_lds(S1, 17, c, li, g, 1.0);
-        const double4_t c2 = mm16_lds(S1, 17, IU + 16 * kT32Ld + 16, kT32Ld, li, g);
-        st16_lds(IU + 16, kT32Ld, c2, li, g, -1.0);
-    } else if (wave == 1) {   // L^{-1}_10 = -L11^{-1} L10 L00^{-1}
-        const double4_t c = mm16_lds(T + 16 * kT32Ld, kT32Ld, IL, kT32Ld, li, g);
+    } else {                  // L10 L00^{-1}
+        const double4_t c = mm16_lds(T + 16 * kT32Ld, kT32Ld, IL0, 17, li, g);
         st16_lds(S2, 17, c, li, g, 1.0);
-        const double4_t c2 = mm16_lds(IL + 16 * kT32Ld + 16, kT32Ld, S2, 17, li, g);
-        st16_lds(IL + 16 * kT32Ld, kT32Ld, c2, li, g, -1.0);
-    } else if (wave == 2) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            IU[(16 + g + 4 * r) * kT32Ld + li] = 0.0;
-            IL[(g + 4 * r) * kT32Ld + 16 + li] = 0.0;
-        }
     }
-    if (lane == 0 && bad < w) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
     __syncthreads();
-    // every tile's inverses are kept (slot s): the next step reads them, and
-    // so do the tiled triangular solves after the factorization
-    const bool keep = L.offW >= 0;
-    double *__restrict__ iLw = W + 128 * (size_t)b + (size_t)s * 2048;
-    for (int e = tid; e < 1024; e += 256) {
-        const int row = e >> 5, col = e & 31;
-        if (row < w && col < w) D[(size_t)(rI + col) * b + rI + row] = T[row * kT32Ld + col];
-        if (keep) {
-            iLw[e] = IL[row * kT32Ld + col];
-            iLw[1024 + e] = IU[row * kT32Ld + col];
+    if (wave >= 2 && keep) {
+        double4_t c = {0.0, 0.0, 0.0, 0.0};
+        if (wave == 2) {      // L^{-1}_10 = -L11^{-1} (L10 L00^{-1})
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(e[kk], S2[(g + 4 * kk) * 17 + li], c, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) iLw[(16 + g + 4 * r) * 32 + li] = -c[r];
+        } else {              // U^{-1}_01 = -(U00^{-1} U01) U11^{-1}
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(S1[li * 17 + g + 4 * kk], e[kk], c, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) iUw[(g + 4 * r) * 32 + 16 + li] = -c[r];
         }
     }
 }
@@ -1134,10 +1223,12 @@ hipError_t launch_getrf_tile32(const DevPlan &d, const int32_t *lvl, int nlev, i
     if (nlev <= 0 || s >= max_nt) return hipSuccess;
     const int m = max_nt - s;
     const unsigned gx = s == 0 ? (unsigned)(2 * max_nt - 1) : (unsigned)(m * m);
-    const int use_one = (nlev == 1 && one) ? 1 : 0;
-    const LevelDev arg = use_one ? *one : LevelDev{};
-    hipLaunchKernelGGL(k_getrf_tile32, dim3(gx, (unsigned)nlev), dim3(256), 0, st, d.slab, d.levels, lvl, s,
-                       d.tgetrf, d.info, arg, use_one);
+    if (nlev == 1 && one)
+        hipLaunchKernelGGL(k_getrf_tile32<true>, dim3(gx, 1), dim3(256), 0, st, d.slab, d.levels, lvl, s, d.tgetrf,
+                           d.info, *one);
+    else
+        hipLaunchKernelGGL(k_getrf_tile32<false>, dim3(gx, (unsigned)nlev), dim3(256), 0, st, d.slab, d.levels, lvl,
+                           s, d.tgetrf, d.info, LevelDev{});
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ FLAGS = [
     "-pthread",
     # no packed fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the first kernel arguments arrive in scalar registers at launch
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-I" + os.path.join(ROOT, "include"),
     "-I" + os.path.join(HERE, "csrc"),
 ]

@@ -972,7 +972,9 @@ __device__ __forceinline__ int lu16s(double (&a)[4], double (&e)[4], int li, int
 //               waves 0, 1 form U00^{-1} U01 and L10 L00^{-1};
 //   waves 2, 3: U^{-1}_01 = -U00^{-1} U01 U11^{-1}, L^{-1}_10 = -L11^{-1} L10 L00^{-1}.
 // Every result goes to global memory from the registers that hold it.  With
-// ONE the wave has a single level, whose record is the kernel argument one.
+// ONE the wave has a single level, whose fields the kernel needs are its
+// first arguments (b1, r01, offD1, offW1: preloaded into scalar registers at
+// launch, no load before the first address is known).
 // Panel copies and inverses live in the level's work region: two copies of
 // 64 b doubles by step parity (tile column b x 32, tile row 32 x b
 // column-major), then the 32 x 32 inverses of L and U (row-major) of every
@@ -980,19 +982,28 @@ __device__ __forceinline__ int lu16s(double (&a)[4], double (&e)[4], int li, int
 constexpr int kT32Ld = 33;
 
 template <bool ONE>
-__global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                                      const int32_t *__restrict__ lvl, int s,
-                                                      double *__restrict__ work,
-                                                      unsigned long long *__restrict__ info, LevelDev one) {
+__global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, int64_t offD1, int64_t offW1,
+                                                      double *__restrict__ slab, double *__restrict__ work,
+                                                      unsigned long long *__restrict__ info,
+                                                      const LevelDev *__restrict__ levels,
+                                                      const int32_t *__restrict__ lvl) {
     __shared__ double xch[2][4][4][64];   // [lt / ut][wave][r][lane]
     __shared__ double T[32 * kT32Ld];
     __shared__ double IL0[16 * 17], IU0[16 * 17], S1[16 * 17], S2[16 * 17];
-    LevelDev L;
-    if constexpr (ONE)
-        L = one;
-    else
-        L = levels[lvl[blockIdx.y]];
-    const int b = L.b;
+    int b, r0;
+    int64_t offD, offW;
+    if constexpr (ONE) {
+        b = b1;
+        r0 = r01;
+        offD = offD1;
+        offW = offW1;
+    } else {
+        const LevelDev &L = levels[lvl[blockIdx.y]];
+        b = L.b;
+        r0 = L.r0;
+        offD = L.offD;
+        offW = L.offW;
+    }
     const int nt = (b + 31) >> 5;
     if (s >= nt) return;
     const int q = blockIdx.x;
@@ -1007,8 +1018,8 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         I = s + q / m;
         J = s + q - (q / m) * m;
     }
-    double *__restrict__ D = slab + L.offD;
-    double *__restrict__ W = work + (L.offW >= 0 ? L.offW : 0);
+    double *__restrict__ D = slab + offD;
+    double *__restrict__ W = work + (offW >= 0 ? offW : 0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
     const int qi = wave >> 1, qj = wave & 1;
     const int rI = 32 * I, cJ = 32 * J;
@@ -1107,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         T[row * kT32Ld + col] = v;
     }
     __syncthreads();
-    const bool keep = L.offW >= 0;
+    const bool keep = offW >= 0;
     double *__restrict__ iLw = W + 128 * (size_t)b + (size_t)s * 2048;   // row-major 32 x 32
     double *__restrict__ iUw = iLw + 1024;
     double *__restrict__ Dt = D + (size_t)rI * b + rI;                   // the tile, column-major, ld b
@@ -1117,7 +1128,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
 #pragma unroll
         for (int t = 0; t < 4; ++t) a[t] = T[li * kT32Ld + g + 4 * t];
         const int bad = lu16s<false>(a, e, li, g);
-        if (lane == 0 && bad < min(16, w)) atomicMin(info, (unsigned long long)(L.r0 + rI + bad));
+        if (lane == 0 && bad < min(16, w)) atomicMin(info, (unsigned long long)(r0 + rI + bad));
         double4_t c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
@@ -1178,7 +1189,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(double *__restrict__ slab,
         for (int t = 0; t < 4; ++t) a[t] = c[t];
         if (tr) {
             const int bad = lu16s<false>(a, e, li, g);
-            if (lane == 0 && bad < w - 16) atomicMin(info, (unsigned long long)(L.r0 + rI + 16 + bad));
+            if (lane == 0 && bad < w - 16) atomicMin(info, (unsigned long long)(r0 + rI + 16 + bad));
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int col = 16 + g + 4 * t;
@@ -1224,11 +1235,11 @@ hipError_t launch_getrf_tile32(const DevPlan &d, const int32_t *lvl, int nlev, i
     const int m = max_nt - s;
     const unsigned gx = s == 0 ? (unsigned)(2 * max_nt - 1) : (unsigned)(m * m);
     if (nlev == 1 && one)
-        hipLaunchKernelGGL(k_getrf_tile32<true>, dim3(gx, 1), dim3(256), 0, st, d.slab, d.levels, lvl, s, d.tgetrf,
-                           d.info, *one);
+        hipLaunchKernelGGL(k_getrf_tile32<true>, dim3(gx, 1), dim3(256), 0, st, s, one->b, one->r0, one->offD,
+                           one->offW, d.slab, d.tgetrf, d.info, d.levels, lvl);
     else
-        hipLaunchKernelGGL(k_getrf_tile32<false>, dim3(gx, (unsigned)nlev), dim3(256), 0, st, d.slab, d.levels, lvl,
-                           s, d.tgetrf, d.info, LevelDev{});
+        hipLaunchKernelGGL(k_getrf_tile32<false>, dim3(gx, (unsigned)nlev), dim3(256), 0, st, s, 0, 0, (int64_t)0,
+                           (int64_t)0, d.slab, d.tgetrf, d.info, d.levels, lvl);
     return hipGetLastError();
 }
 

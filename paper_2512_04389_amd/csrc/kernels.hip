@@ -976,9 +976,10 @@ __device__ __forceinline__ int lu16s(double (&a)[4], double (&e)[4], int li, int
 // first arguments (b1, r01, offD1, offW1: preloaded into scalar registers at
 // launch, no load before the first address is known).
 // Panel copies and inverses live in the level's work region: two copies of
-// 64 b doubles by step parity (tile column b x 32, tile row 32 x b
-// column-major), then the 32 x 32 inverses of L and U (row-major) of every
-// diagonal tile (kept for the solves).
+// 64 b doubles by step parity (tile column b x 32 row-major, tile row 32 x b
+// column-major), then the 32 x 32 inverses of L (row-major) and U
+// (column-major) of every diagonal tile (kept for the solves): every operand
+// of the panel products is then contiguous in the inner index.
 constexpr int kT32Ld = 33;
 
 template <bool ONE>
@@ -1035,20 +1036,22 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
     for (int r = 0; r < 4; ++r) acc[r] = D[colc * b + min(row0 + g + 4 * r, b - 1)];
     if (s >= 1) {
         const int p = s - 1;
-        const double *__restrict__ Pc = W + (size_t)(p & 1) * 64 * b;   // tile column p, b x 32
+        const double *__restrict__ Pc = W + (size_t)(p & 1) * 64 * b;   // tile column p, b x 32 (ld 32)
         const double *__restrict__ Pr = Pc + (size_t)32 * b;           // tile row p, 32 x b (ld 32)
-        const double *__restrict__ iLg = W + 128 * (size_t)b + (size_t)p * 2048;
-        const double *__restrict__ iUg = iLg + 1024;
+        const double *__restrict__ iLg = W + 128 * (size_t)b + (size_t)p * 2048;   // row-major
+        const double *__restrict__ iUg = iLg + 1024;                               // column-major
         const int rowq = row0 + li;
         const bool rowok = rowq < b;
         const int rowc = min(rowq, b - 1);
+        // product step kk takes the inner index k = 8 g + kk in lane group g
+        // (the same for both operands), eight consecutive doubles per lane
         double4_t lt = {0.0, 0.0, 0.0, 0.0}, ut = {0.0, 0.0, 0.0, 0.0};
         double xa[8], ya[8], xb[8], yb[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-            const int k = 4 * kk + g;
-            xa[kk] = iUg[k * 32 + 16 * qj + li];                           // iU(k, 16 qj + li)
-            ya[kk] = Pc[(size_t)k * b + rowc];                             // A(I, p)(16 qi + li, k)
+            const int k = 8 * g + kk;
+            xa[kk] = iUg[(16 * qj + li) * 32 + k];                         // iU(k, 16 qj + li)
+            ya[kk] = Pc[(size_t)rowc * 32 + k];                            // A(I, p)(16 qi + li, k)
             xb[kk] = iLg[(16 * qi + li) * 32 + k];                         // iL(16 qi + li, k)
             yb[kk] = Pr[colc * 32 + k];                                    // A(p, J)(k, 16 qj + li)
         }
@@ -1090,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = row0 + g + 4 * r;
-                    if (row < b) Pc[(size_t)(16 * qj + li) * b + row] = acc[r];
+                    if (row < b) Pc[(size_t)row * 32 + 16 * qj + li] = acc[r];
                 }
             }
         } else if (I == s) {   // next panel, tile row
@@ -1120,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
     __syncthreads();
     const bool keep = offW >= 0;
     double *__restrict__ iLw = W + 128 * (size_t)b + (size_t)s * 2048;   // row-major 32 x 32
-    double *__restrict__ iUw = iLw + 1024;
+    double *__restrict__ iUw = iLw + 1024;                               // column-major 32 x 32
     double *__restrict__ Dt = D + (size_t)rI * b + rI;                   // the tile, column-major, ld b
     double a[4], e[4];
     if (wave == 0) {
@@ -1160,8 +1163,8 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
         for (int t = 0; t < 4; ++t) {
             IU0[(g + 4 * t) * 17 + li] = e[t];
             if (keep) {
-                iUw[(g + 4 * t) * 32 + li] = e[t];
-                iUw[(16 + g + 4 * t) * 32 + li] = 0.0;                      // U^{-1}_10
+                iUw[li * 32 + g + 4 * t] = e[t];
+                iUw[li * 32 + 16 + g + 4 * t] = 0.0;                        // U^{-1}_10
             }
         }
         st16_lds(T + 16 * kT32Ld, kT32Ld, c, li, g, 1.0);
@@ -1200,7 +1203,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
             (void)lu16s<true>(a, e, li, g);
             if (keep) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) iUw[(16 + g + 4 * t) * 32 + 16 + li] = e[t];
+                for (int t = 0; t < 4; ++t) iUw[(16 + li) * 32 + 16 + g + 4 * t] = e[t];
             }
         }
     } else if (wave == 0) {   // U00^{-1} U01
@@ -1224,7 +1227,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
             for (int kk = 0; kk < 4; ++kk)
                 c = __builtin_amdgcn_mfma_f64_16x16x4f64(S1[li * 17 + g + 4 * kk], e[kk], c, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) iUw[(g + 4 * r) * 32 + 16 + li] = -c[r];
+            for (int r = 0; r < 4; ++r) iUw[(16 + li) * 32 + g + 4 * r] = -c[r];
         }
     }
 }
@@ -2435,11 +2438,13 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
     const bool rhs_ok = li < nc;
     double *__restrict__ Xc = Wx + (size_t)(rhs_ok ? li : 0) * n + L.r0;   // this lane's right-hand side
     const bool use_l = (fwd != 0) == (trans == 0);   // M and A from L (else from U)
-    // M_s (row-major 32 x 32 inverses of tile s): element (i, k) of the
-    // operator applied, i.e. iL / iU, transposed for the transposed solve
+    // M_s (32 x 32 inverses of tile s, iL row-major, iU column-major):
+    // element (i, k) of the operator applied, i.e. iL / iU, transposed for
+    // the transposed solve
+    const bool mtr = use_l ? trans != 0 : trans == 0;
     auto mload = [&](int s2, int i, int k) -> double {
         const double *Mb = Inv + (size_t)s2 * 2048 + (use_l ? 0 : 1024);
-        return trans ? Mb[k * 32 + i] : Mb[i * 32 + k];
+        return mtr ? Mb[k * 32 + i] : Mb[i * 32 + k];
     };
     // x of tile s2 (32 rows) = M b_s2 in result layout: half h, lane (li, g),
     // element r -> row 16 h + g + 4 r, right-hand side li

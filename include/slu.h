@@ -271,13 +271,15 @@ typedef struct {
     int32_t getrf_tile;           /* slu_set_getrf_tile                      */
     int32_t panel_blocked;        /* slu_set_panel_blocked                   */
     int32_t graph;                /* slu_set_graph                           */
+    int32_t lookahead;            /* slu_set_lookahead                       */
     double ms;                    /* median of reps factors (HIP events)     */
 } slu_tune_entry;
 
 /* Autotuner of the launch shapes for this handle's pattern and values (the
  * batch of independent systems included): factors with each of a fixed set
  * of settings (tiled GETRF with 32- or 16-row tiles or the chunked GETRF,
- * blocked or tile-wise panel solves, launch by launch or graph replay), one
+ * blocked or tile-wise panel solves, launch by launch or graph replay, with
+ * or without lookahead), one
  * warm-up and reps timed factors each on `stream`, keeps the setting with the
  * smallest median and factors once more with it, so the handle ends factored
  * and set to the choice.  table (capacity entries, may be NULL when capacity
@@ -297,6 +299,29 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
  * tile step; one workgroup per block otherwise).  Same results up to
  * rounding.  SLU_ERR_ARG for a negative min_rows. */
 int slu_set_solve_tiled(slu_handle *h, int min_rows);
+
+/* Lookahead of the Schur updates (Algorithm 1's SSSSM; the level order of
+ * Section 3.2): with enable = 1 the updates of a wave whose
+ * levels have pairwise disjoint targets (one launch round) are split by
+ * target.  The updates of the next wave's diagonal blocks and panels run on
+ * the factor's stream as before; the updates that reach only later waves run
+ * on a second stream of the library's own (default priority) while the next
+ * wave factors its diagonal blocks and solves its panels, and the next
+ * updates on the factor's stream wait for them.  Waves of several rounds run
+ * their updates on the factor's stream.  max_groups (a multiple of 8; 0: one
+ * workgroup per tile) caps the workgroups of a deferred launch, which then
+ * walk its tiles, so that they leave room on every CU for the factor's
+ * stream.  Default: disabled (256 workgroups once enabled).  The deferred
+ * updates share the CUs and HBM with the next wave's latency-bound launches
+ * and slow them down, so lookahead pays where those updates are large next
+ * to the diagonal work (a chain of dense blocks) and costs elsewhere; the
+ * autotuner (slu_autotune) tries both.
+ * Every target receives its updates in the same order as without lookahead,
+ * so the factors are the same bit for bit.  Not used under per-kernel timing
+ * (slu_set_profiling).  A captured graph is recaptured (the graph then
+ * holds both streams' launches).  SLU_ERR_ARG unless enable is 0 or 1 and
+ * max_groups a non-negative multiple of 8. */
+int slu_set_lookahead(slu_handle *h, int enable, int max_groups);
 
 /* Blocked panel solves (Algorithm 1's GESSM / TSTRF, the panels of block
  * column i times the inverse of the coupled triangle of L_ii or U_ii): with

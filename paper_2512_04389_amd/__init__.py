@@ -255,6 +255,12 @@ class SparseLU:
         ``slu_set_panel_blocked``)."""
         check(lib.slu_set_panel_blocked(self._h, 1 if enable else 0), "slu_set_panel_blocked")
 
+    def set_lookahead(self, enable=True, max_groups=256):
+        """Schur updates that reach only later waves on a second stream,
+        overlapping the next wave's diagonal and panel work, in launches of
+        at most ``max_groups`` workgroups (see ``slu_set_lookahead``)."""
+        check(lib.slu_set_lookahead(self._h, 1 if enable else 0, int(max_groups)), "slu_set_lookahead")
+
     def autotune(self, values, reps=2, stream=None):
         """Try the library's launch-shape settings on these values and keep
         the fastest (``slu_autotune``); returns the table of settings tried

@@ -47,7 +47,7 @@ EXPORTS = [
     "slu_get_kernel_times", "slu_value_gradient", "slu_set_precision", "slu_solve_refined",
     "slu_analyze_batch", "slu_set_graph", "slu_last_hip_error", "slu_hip_error_string",
     "slu_set_host_threads", "slu_set_getrf_split", "slu_set_getrf_tiled", "slu_solve_noalloc", "slu_set_getrf_tile",
-    "slu_set_panel_blocked", "slu_set_solve_tiled", "slu_autotune",
+    "slu_set_panel_blocked", "slu_set_solve_tiled", "slu_autotune", "slu_set_lookahead",
 ]
 
 
@@ -72,6 +72,7 @@ class slu_tune_entry(ctypes.Structure):
         ("getrf_tile", ctypes.c_int32),
         ("panel_blocked", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("lookahead", ctypes.c_int32),
         ("ms", ctypes.c_double),
     ]
 
@@ -143,6 +144,7 @@ def _load():
         "slu_solve_noalloc": (i32, [hp, p, p, i64, i64, i32, p]),
         "slu_set_getrf_tile": (i32, [hp, ctypes.c_int]),
         "slu_set_panel_blocked": (i32, [hp, ctypes.c_int]),
+        "slu_set_lookahead": (i32, [hp, ctypes.c_int, ctypes.c_int]),
         "slu_set_solve_tiled": (i32, [hp, ctypes.c_int]),
         "slu_autotune": (i32, [hp, p, i32, p, i32, ctypes.POINTER(ctypes.c_int), p]),
         "slu_last_hip_error": (i32, []),

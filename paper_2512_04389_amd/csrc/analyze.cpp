@@ -830,6 +830,16 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
             w.end = (int32_t)an.wave_levels.size();
             an.waves.push_back(w);
         }
+        // coupled rows of every level up to its last row in a block of the
+        // next wave (R is sorted, segments go by block)
+        std::vector<int32_t> wave_of(p, 0), crit_rows(p, 0);
+        for (size_t wi = 0; wi < an.waves.size(); ++wi)
+            for (int32_t q = an.waves[wi].begin; q < an.waves[wi].end; ++q) wave_of[an.wave_levels[q]] = (int32_t)wi;
+        for (int64_t i = 0; i < p; ++i) {
+            const LevelDev &L = an.levels[i];
+            for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi)
+                if (wave_of[an.segs[sgi].blk] == wave_of[i] + 1) crit_rows[i] = an.segs[sgi].start + an.segs[sgi].len;
+        }
         // SSSSM rounds: levels of a wave whose sets of target blocks are
         // disjoint (first fit, in level order); a level whose blocks meet an
         // earlier level's goes to a later round, so every target receives its
@@ -866,15 +876,24 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 int32_t mmax = 0;
                 for (int32_t i : r) mmax = std::max(mmax, an.levels[i].m);
                 ri.tile = mmax < kSsssmSmallM ? 32 : kSsssmTile;
-                int64_t t = 0;
+                int64_t t = 0, tc = 0, tr = 0;
                 for (int32_t i : r) {
-                    const int64_t nt = ((int64_t)an.levels[i].m + ri.tile - 1) / ri.tile;
+                    LevelDev &L = an.levels[i];
+                    const int64_t nt = ((int64_t)L.m + ri.tile - 1) / ri.tile;
+                    const int64_t nc = std::min<int64_t>(nt, ((int64_t)crit_rows[i] + ri.tile - 1) / ri.tile);
+                    L.sscrit = (int32_t)nc;
                     an.round_levels.push_back(i);
                     an.round_tiles.push_back(t);
+                    an.round_tiles.push_back(tc);
+                    an.round_tiles.push_back(tr);
                     t += nt * nt;
+                    tr += (nt - nc) * (nt - nc);
+                    tc += nt * nt - (nt - nc) * (nt - nc);
                 }
                 ri.end = (int32_t)an.round_levels.size();
                 ri.tiles = t;
+                ri.tiles_c = tc;
+                ri.tiles_r = tr;
                 if (t >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
                 an.rounds.push_back(ri);
             }

@@ -48,6 +48,10 @@ struct LevelDev {
     int32_t sch_begin, sch_end; // triangular-solve chunks in schunks
     int32_t sb_begin, sb_end;   // solve batch records (sbatch pairs), end = sentinel
     int64_t sitem;              // first solve item of the level in sitems
+    // Schur-update tile rows (at its round's tile edge) that cover every
+    // coupled row of the next wave's blocks: the tiles in those rows or
+    // columns update the next wave; the others only later waves
+    int32_t sscrit, pad2;
 };
 
 // One column chunk of the right-looking GETRF of D_i: local columns
@@ -64,6 +68,7 @@ struct ChunkDev {
 struct RoundInfo {
     int32_t begin, end;         // range in round_levels
     int64_t tiles;              // SSSSM workgroups of the round
+    int64_t tiles_c, tiles_r;   // of which update the next wave / only later waves
     int32_t tile, pad;          // tile edge (64, or 32 when every level is small)
 };
 
@@ -125,7 +130,9 @@ struct Analysis {
     std::vector<int32_t> wave_levels;
     std::vector<RoundInfo> rounds;
     std::vector<int32_t> round_levels;   // levels of every round, consecutive
-    std::vector<int64_t> round_tiles;    // first SSSSM workgroup of each level within its round
+    // first SSSSM workgroup of each level within its round, three per level:
+    // counting all its tiles, the tiles that update the next wave, the rest
+    std::vector<int64_t> round_tiles;
     std::vector<int32_t> tslot_off;      // per wave_levels entry: first triangle-gather workgroup of the level in its wave
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles
     std::vector<int32_t> trow_idx;

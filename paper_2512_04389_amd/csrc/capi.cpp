@@ -51,6 +51,15 @@ struct slu_handle {
     // inverted diagonal tiles
     int solve_tiled_rows = 256;
     std::vector<char> wave_tinv;
+    // Schur updates of a wave (of one round) that reach only later waves run
+    // on a second stream (default priority) while the next wave factors its
+    // diagonal blocks and panels; the updates of the next wave's blocks stay
+    // on the factor's stream.  Events: this wave's updates of the next wave
+    // are done / the second stream's updates so far are done.
+    bool lookahead = false;
+    int la_groups = 256;        // workgroups of a deferred update launch (0: one per tile)
+    hipStream_t la_stream = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
 };
 
 namespace {
@@ -501,10 +510,28 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
     SLU_LAUNCH(slu::launch_scatter(d, values, s));
     SLU_END();
     h->wave_tinv.assign(an.waves.size(), 0);
+    // lookahead (not under per-kernel timing, which times the classes apart)
+    const bool la = h->lookahead && !h->profiling;
+    if (la) {
+        if (!h->la_stream && hip_failed(hipStreamCreateWithFlags(&h->la_stream, hipStreamNonBlocking)))
+            return SLU_ERR_HIP;
+        if (!h->ev_panel && hip_failed(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming)))
+            return SLU_ERR_HIP;
+        if (!h->ev_rest && hip_failed(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming)))
+            return SLU_ERR_HIP;
+    }
+    // wave whose deferred updates the factor's stream has not waited for yet
+    // (-1: none); they reach waves two or more later, so wave wi waits for
+    // them before its first launch at the latest
+    int64_t rest_wave = -1;
     for (size_t wi = 0; wi < an.waves.size(); ++wi) {
         const slu::WaveInfo &w = an.waves[wi];
         const int nlev = w.end - w.begin;
         const int32_t *lv = d.wave_levels + w.begin;
+        if (rest_wave >= 0 && rest_wave + 2 <= (int64_t)wi) {
+            if (hip_failed(hipStreamWaitEvent(s, h->ev_rest, 0))) return SLU_ERR_HIP;
+            rest_wave = -1;
+        }
         SLU_BEGIN(SLU_KERNEL_GETRF);
         // the tiled GETRF when selected, and for waves whose chunked GETRF
         // would not fit the LDS
@@ -569,11 +596,39 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         }
         if (w.round_end > w.round_begin) {
             SLU_BEGIN(SLU_KERNEL_SSSSM);
-            for (int r = w.round_begin; r < w.round_end; ++r)
-                SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], h->precision == SLU_PRECISION_FP32, s));
+            const bool f32 = h->precision == SLU_PRECISION_FP32;
+            if (!la) {
+                for (int r = w.round_begin; r < w.round_end; ++r)
+                    SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], f32, 0, 0, s));
+            } else {
+                // only a wave with one round is split: the rounds of a wave
+                // share targets, so a later round's updates must not run
+                // beside an earlier round's deferred ones
+                const bool split = w.round_end - w.round_begin == 1;
+                const int64_t rest = split ? an.rounds[w.round_begin].tiles_r : 0;
+                // the updates on this stream come after the previous wave's
+                // deferred updates (they may share targets)
+                if (rest_wave >= 0) {
+                    if (hip_failed(hipStreamWaitEvent(s, h->ev_rest, 0))) return SLU_ERR_HIP;
+                    rest_wave = -1;
+                }
+                for (int r = w.round_begin; r < w.round_end; ++r)
+                    SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], f32, split ? 1 : 0, 0, s));
+                // the deferred updates start once the next wave's are done,
+                // so they fill the next wave's diagonal and panel phase
+                if (rest > 0 && hip_failed(hipEventRecord(h->ev_panel, s))) return SLU_ERR_HIP;
+                if (rest > 0) {
+                    hipStream_t b = h->la_stream;
+                    if (hip_failed(hipStreamWaitEvent(b, h->ev_panel, 0))) return SLU_ERR_HIP;
+                    SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[w.round_begin], f32, 2, h->la_groups, b));
+                    if (hip_failed(hipEventRecord(h->ev_rest, b))) return SLU_ERR_HIP;
+                    rest_wave = (int64_t)wi;
+                }
+            }
             SLU_END();
         }
     }
+    if (rest_wave >= 0 && hip_failed(hipStreamWaitEvent(s, h->ev_rest, 0))) return SLU_ERR_HIP;
 #undef SLU_BEGIN
 #undef SLU_LAUNCH
 #undef SLU_END
@@ -711,6 +766,17 @@ int slu_set_getrf_tile(slu_handle *h, int tile) {
     return SLU_OK;
 }
 
+int slu_set_lookahead(slu_handle *h, int enable, int max_groups) {
+    if (!h || (enable != 0 && enable != 1) || max_groups < 0 || max_groups % 8 != 0) return SLU_ERR_ARG;
+    h->lookahead = enable != 0;
+    h->la_groups = max_groups;
+    if (h->gexec) {   // a captured graph holds the other launch sequence
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    return SLU_OK;
+}
+
 int slu_set_panel_blocked(slu_handle *h, int enable) {
     if (!h || (enable != 0 && enable != 1)) return SLU_ERR_ARG;
     h->panel_blocked = enable != 0;
@@ -726,12 +792,13 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
     if (!h || (!values && h->an.nnz_a > 0) || reps < 1 || capacity < 0 || (capacity > 0 && !table)) return SLU_ERR_ARG;
     if (!h->bound) return SLU_ERR_STATE;
     hipStream_t s = (hipStream_t)stream;
-    // the launch-shape settings tried: GETRF path x panel path x graph replay
+    // the launch-shape settings tried: GETRF path x panel path x graph
+    // replay x lookahead
     struct Cfg {
-        int tiled_rows, tile, panel, graph;
+        int tiled_rows, tile, panel, graph, lookahead;
     };
-    const Cfg cfgs[] = {{1, 32, 1, 0}, {1, 32, 0, 0}, {1, 16, 1, 0}, {0, 32, 1, 0},
-                        {1, 32, 1, 1}, {1, 16, 1, 1}, {0, 32, 1, 1}};
+    const Cfg cfgs[] = {{1, 32, 1, 0, 0}, {1, 32, 1, 0, 1}, {1, 32, 0, 0, 0}, {1, 16, 1, 0, 0}, {0, 32, 1, 0, 0},
+                        {1, 32, 1, 1, 0}, {1, 32, 1, 1, 1}, {1, 16, 1, 1, 0}, {0, 32, 1, 1, 0}};
     const int ncfg = (int)(sizeof(cfgs) / sizeof(cfgs[0]));
     const bool prof = h->profiling;
     h->profiling = false;
@@ -746,6 +813,7 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
         h->getrf_tiled_rows = cfgs[c].tiled_rows;
         h->getrf_tile = cfgs[c].tile;
         h->panel_blocked = cfgs[c].panel != 0;
+        h->lookahead = cfgs[c].lookahead != 0;
         if (h->gexec) {
             (void)hipGraphExecDestroy(h->gexec);
             h->gexec = nullptr;
@@ -767,6 +835,7 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
             table[n].getrf_tile = cfgs[c].tile;
             table[n].panel_blocked = cfgs[c].panel;
             table[n].graph = cfgs[c].graph;
+            table[n].lookahead = cfgs[c].lookahead;
             table[n].ms = ms;
         }
         ++n;
@@ -782,6 +851,7 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
         h->getrf_tiled_rows = cfgs[best].tiled_rows;
         h->getrf_tile = cfgs[best].tile;
         h->panel_blocked = cfgs[best].panel != 0;
+        h->lookahead = cfgs[best].lookahead != 0;
         if (h->gexec) {
             (void)hipGraphExecDestroy(h->gexec);
             h->gexec = nullptr;
@@ -1014,6 +1084,9 @@ void slu_free(slu_handle *h) {
     if (!h) return;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->la_stream) (void)hipStreamDestroy(h->la_stream);
+    if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+    if (h->ev_rest) (void)hipEventDestroy(h->ev_rest);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }

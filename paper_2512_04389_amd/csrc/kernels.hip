@@ -1914,33 +1914,58 @@ constexpr int kSsKC = 16;               // inner indices per LDS slice
 // (rounds of small levels, for more workgroups).  Workgroups are dealt to
 // the eight XCDs in turn, so the tile number is remapped to give each XCD a
 // contiguous run of row-major tiles: its share of P_i stays in its L2.
+// mode selects the tiles of each level: all (0); those in its first sscrit
+// tile rows or columns, which hold every target of the next wave's blocks
+// (1: tile rows 0 .. sscrit - 1 whole, then the first sscrit columns of the
+// later rows); the others (2: the square of later rows and columns).  A grid
+// smaller than the round's tile count walks the tiles (tile, tile + grid,
+// ...; the grid a multiple of 8 keeps every tile on its XCD): the deferred
+// updates that run beside the next wave's work take few workgroups, so they
+// leave room on every CU for the launches of the factor's own stream.
 template <bool F32, int TT>
-__global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
-                                               const int32_t *__restrict__ rlev, const int64_t *__restrict__ rtile,
-                                               int nlev, const int32_t *__restrict__ rseg,
-                                               const int64_t *__restrict__ stgt,
-                                               const int32_t *__restrict__ maps) {
+__device__ __forceinline__ void ssssm_tile(int64_t bid, int64_t total, double *__restrict__ slab,
+                                           const LevelDev *__restrict__ levels, const int32_t *__restrict__ rlev,
+                                           const int64_t *__restrict__ rtile, int nlev,
+                                           const int32_t *__restrict__ rseg, const int64_t *__restrict__ stgt,
+                                           const int32_t *__restrict__ maps, int mode) {
     typedef typename std::conditional<F32, float, double>::type elem;
     typedef typename std::conditional<F32, float4_t, double4_t>::type acc4;
     constexpr int NT = TT == 64 ? 256 : 64;
     constexpr int LD = TT + 4;             // LDS row stride
     __shared__ elem As[2][kSsKC][LD], Bs[2][kSsKC][LD];
-    int64_t bid = blockIdx.x;
     {
-        const int64_t total = gridDim.x, q = total >> 3, r = total & 7;
+        const int64_t q = total >> 3, r = total & 7;
         const int64_t x = bid & 7, i = bid >> 3;
         bid = x * q + (x < r ? x : r) + i;
     }
     int lo = 0, hi = nlev - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (rtile[mid] <= bid) lo = mid; else hi = mid - 1;
+        if (rtile[3 * mid + mode] <= bid) lo = mid; else hi = mid - 1;
     }
     const LevelDev L = levels[rlev[lo]];
-    const int tile = (int)(bid - rtile[lo]);
+    const int tile = (int)(bid - rtile[3 * lo + mode]);
     const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
     const int nt = (m + TT - 1) / TT;
-    const int ti = tile / nt, tj = tile - ti * nt;
+    int ti, tj;
+    if (mode == 0) {
+        ti = tile / nt;
+        tj = tile - ti * nt;
+    } else if (mode == 1) {
+        const int nc = L.sscrit;
+        if (tile < nc * nt) {
+            ti = tile / nt;
+            tj = tile - ti * nt;
+        } else {
+            const int q = tile - nc * nt;
+            ti = nc + q / nc;
+            tj = q - (q / nc) * nc;
+        }
+    } else {
+        const int nc = L.sscrit, nr = nt - nc;
+        ti = nc + tile / nr;
+        tj = nc + tile - (tile / nr) * nr;
+    }
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int wr = TT == 64 ? wave >> 1 : 0, wc = TT == 64 ? wave & 1 : 0;
@@ -2093,26 +2118,40 @@ __global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restric
     }
 }
 
-hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, hipStream_t s) {
-    if (r.tiles <= 0) return hipSuccess;
+template <bool F32, int TT>
+__global__ __launch_bounds__(TT == 64 ? 256 : 64) void k_ssssm(double *__restrict__ slab, const LevelDev *__restrict__ levels,
+                                               const int32_t *__restrict__ rlev, const int64_t *__restrict__ rtile,
+                                               int nlev, const int32_t *__restrict__ rseg,
+                                               const int64_t *__restrict__ stgt,
+                                               const int32_t *__restrict__ maps, int mode, int64_t total) {
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        ssssm_tile<F32, TT>(bid, total, slab, levels, rlev, rtile, nlev, rseg, stgt, maps, mode);
+        __syncthreads();   // the next tile restages the LDS operands
+    }
+}
+
+hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, int mode, int max_groups,
+                              hipStream_t s) {
+    const int64_t tiles = mode == 0 ? r.tiles : (mode == 1 ? r.tiles_c : r.tiles_r);
+    if (tiles <= 0) return hipSuccess;
     const int nlev = r.end - r.begin;
     const int32_t *rl = d.round_levels + r.begin;
-    const int64_t *rt = d.round_tiles + r.begin;
-    const dim3 g((unsigned)r.tiles);
+    const int64_t *rt = d.round_tiles + 3 * (size_t)r.begin;
+    const dim3 g((unsigned)(max_groups > 0 && tiles > max_groups ? max_groups : tiles));
     if (r.tile == 64) {
         if (f32)
             hipLaunchKernelGGL((k_ssssm<true, 64>), g, dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
-                               d.stgt, d.maps);
+                               d.stgt, d.maps, mode, tiles);
         else
             hipLaunchKernelGGL((k_ssssm<false, 64>), g, dim3(256), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
-                               d.stgt, d.maps);
+                               d.stgt, d.maps, mode, tiles);
     } else {
         if (f32)
             hipLaunchKernelGGL((k_ssssm<true, 32>), g, dim3(64), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
-                               d.stgt, d.maps);
+                               d.stgt, d.maps, mode, tiles);
         else
             hipLaunchKernelGGL((k_ssssm<false, 32>), g, dim3(64), 0, s, d.slab, d.levels, rl, rt, nlev, d.rseg,
-                               d.stgt, d.maps);
+                               d.stgt, d.maps, mode, tiles);
     }
     return hipGetLastError();
 }

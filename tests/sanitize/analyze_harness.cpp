@@ -78,7 +78,40 @@ bool same_plan(const slu::Analysis &a, const slu::Analysis &b) {
     return a.perm == b.perm && a.s_colptr == b.s_colptr && a.s_rowidx == b.s_rowidx && a.bptr == b.bptr &&
            a.maps == b.maps && a.stgt == b.stgt && a.chunk_rows == b.chunk_rows && a.slot == b.slot &&
            a.wave_levels == b.wave_levels && a.round_levels == b.round_levels && a.sitems == b.sitems &&
-           a.slab_doubles == b.slab_doubles && a.tgetrf_doubles == b.tgetrf_doubles;
+           a.slab_doubles == b.slab_doubles && a.tgetrf_doubles == b.tgetrf_doubles &&
+           a.round_tiles == b.round_tiles;
+}
+
+// The Schur-update split of every round: critical and other tiles add up to
+// all tiles (three prefix counts per level), and no tile outside a level's
+// first sscrit tile rows and columns holds a coupled row of a block in the
+// next wave.
+bool split_ok(const slu::Analysis &an) {
+    std::vector<int32_t> wave_of(an.levels.size(), 0);
+    for (size_t wi = 0; wi < an.waves.size(); ++wi)
+        for (int32_t q = an.waves[wi].begin; q < an.waves[wi].end; ++q) wave_of[an.wave_levels[q]] = (int32_t)wi;
+    if (an.round_tiles.size() != 3 * an.round_levels.size()) return false;
+    for (const slu::RoundInfo &r : an.rounds) {
+        if (r.tiles_c + r.tiles_r != r.tiles) return false;
+        int64_t t = 0, tc = 0, tr = 0;
+        for (int32_t q = r.begin; q < r.end; ++q) {
+            if (an.round_tiles[3 * q] != t || an.round_tiles[3 * q + 1] != tc || an.round_tiles[3 * q + 2] != tr)
+                return false;
+            const int32_t i = an.round_levels[q];
+            const slu::LevelDev &L = an.levels[i];
+            const int64_t nt = ((int64_t)L.m + r.tile - 1) / r.tile, nc = L.sscrit;
+            if (nc < 0 || nc > nt) return false;
+            t += nt * nt;
+            tc += nt * nt - (nt - nc) * (nt - nc);
+            tr += (nt - nc) * (nt - nc);
+            for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) {
+                const slu::Segment &g = an.segs[sgi];
+                if (wave_of[g.blk] == wave_of[i] + 1 && (int64_t)(g.start + g.len) > nc * r.tile) return false;
+            }
+        }
+        if (t != r.tiles || tc != r.tiles_c || tr != r.tiles_r) return false;
+    }
+    return true;
 }
 
 int run(const char *name, const Csr &a, slu_options o, const std::vector<int64_t> *seg = nullptr) {
@@ -89,6 +122,10 @@ int run(const char *name, const Csr &a, slu_options o, const std::vector<int64_t
     int rc8 = slu::analyze(a.n, a.rp.data(), a.ci.data(), o, &many, seg);
     if (rc1 != SLU_OK || rc8 != SLU_OK || !same_plan(one, many)) {
         std::fprintf(stderr, "%s: rc %d / %d or plans differ\n", name, rc1, rc8);
+        return 1;
+    }
+    if (!split_ok(one)) {
+        std::fprintf(stderr, "%s: Schur-update split reaches the next wave\n", name);
         return 1;
     }
     std::printf("%s: n %lld levels %lld nnz(S) %lld\n", name, (long long)a.n, (long long)one.p,

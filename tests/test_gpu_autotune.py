@@ -25,7 +25,8 @@ def test_autotune_single_system():
     h = slu.SparseLU(n, rp, ci).bind()
     vals = torch.from_numpy(v).cuda()
     table = h.autotune(vals, reps=2)
-    assert len(table) == 7
+    assert len(table) == 9
+    assert {r["lookahead"] for r in table} == {0, 1}
     assert all(r["ms"] > 0 for r in table)
     assert table[0]["ms"] == min(r["ms"] for r in table)
     assert h.info()["factored"] == 1
@@ -44,7 +45,7 @@ def test_autotune_batch():
     h = slu.SparseLU.batch([(x[0], x[1], x[2]) for x in sy], ordering="grid_nd", grid_dims=[x[4] for x in sy]).bind()
     vals = torch.from_numpy(np.concatenate([x[3] for x in sy])).cuda()
     table = h.autotune(vals, reps=1)
-    assert len(table) == 7
+    assert len(table) == 9
     xs = [synth.random_x(x[0], 1, seed=q) for q, x in enumerate(sy)]
     b = np.concatenate([synth.csr_matvec(x[0], x[1], x[2], x[3], xx) for x, xx in zip(sy, xs)])
     X = h.solve(torch.from_numpy(np.ascontiguousarray(b)).cuda()).cpu().numpy()

@@ -96,7 +96,7 @@ KERNEL_SOURCES = ("paper_2512_04389_amd/csrc/kernels.hip", "paper_2512_04389_amd
                   "paper_2512_04389_amd/csrc/analyze.cpp", "paper_2512_04389_amd/csrc/analyze.hpp",
                   "paper_2512_04389_amd/csrc/capi.cpp")   # capi.cpp: the launch sequence
 KERNEL_SYMBOL = {"getrf": ("k_getrf_wave", "k_getrf_step", "k_getrf_trail", "k_getrf_tile"),
-                 "panel": ("k_tri_gather", "k_panel_solve"), "ssssm": ("k_ssssm",)}
+                 "panel": ("k_tri_gather", "k_panel_solve", "k_tri_binv", "k_panel_blk"), "ssssm": ("k_ssssm",)}
 COPY_BYTES = 256 << 20
 
 

@@ -311,11 +311,11 @@ int slu_set_solve_tiled(slu_handle *h, int min_rows);
  * their updates on the factor's stream.  max_groups (a multiple of 8; 0: one
  * workgroup per tile) caps the workgroups of a deferred launch, which then
  * walk its tiles, so that they leave room on every CU for the factor's
- * stream.  Default: disabled (256 workgroups once enabled).  The deferred
+ * stream.  Default: disabled (512 workgroups once enabled).  The deferred
  * updates share the CUs and HBM with the next wave's latency-bound launches
- * and slow them down, so lookahead pays where those updates are large next
- * to the diagonal work (a chain of dense blocks) and costs elsewhere; the
- * autotuner (slu_autotune) tries both.
+ * (whose waves raise their issue priority above them), so lookahead pays
+ * where those updates are large next to the diagonal work (a chain of dense
+ * blocks) and can cost elsewhere; the autotuner (slu_autotune) tries both.
  * Every target receives its updates in the same order as without lookahead,
  * so the factors are the same bit for bit.  Not used under per-kernel timing
  * (slu_set_profiling).  A captured graph is recaptured (the graph then

@@ -255,7 +255,7 @@ class SparseLU:
         ``slu_set_panel_blocked``)."""
         check(lib.slu_set_panel_blocked(self._h, 1 if enable else 0), "slu_set_panel_blocked")
 
-    def set_lookahead(self, enable=True, max_groups=256):
+    def set_lookahead(self, enable=True, max_groups=512):
         """Schur updates that reach only later waves on a second stream,
         overlapping the next wave's diagonal and panel work, in launches of
         at most ``max_groups`` workgroups (see ``slu_set_lookahead``)."""

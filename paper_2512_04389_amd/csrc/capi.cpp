@@ -57,7 +57,7 @@ struct slu_handle {
     // on the factor's stream.  Events: this wave's updates of the next wave
     // are done / the second stream's updates so far are done.
     bool lookahead = false;
-    int la_groups = 256;        // workgroups of a deferred update launch (0: one per tile)
+    int la_groups = 512;        // workgroups of a deferred update launch (0: one per tile)
     hipStream_t la_stream = nullptr;
     hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
 };

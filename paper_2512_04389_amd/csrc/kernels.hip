@@ -988,6 +988,7 @@ __global__ __launch_bounds__(256) void k_getrf_tile32(int s, int b1, int r01, in
                                                       unsigned long long *__restrict__ info,
                                                       const LevelDev *__restrict__ levels,
                                                       const int32_t *__restrict__ lvl) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     __shared__ double xch[2][4][4][64];   // [lt / ut][wave][r][lane]
     __shared__ double T[32 * kT32Ld];
     __shared__ double IL0[16 * 17], IU0[16 * 17], S1[16 * 17], S2[16 * 17];
@@ -1262,6 +1263,7 @@ __global__ __launch_bounds__(256) void k_tri_gather(const double *__restrict__ s
                                                     const int32_t *__restrict__ Kidx,
                                                     const int32_t *__restrict__ trow_ptr,
                                                     const int32_t *__restrict__ trow_idx) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     __shared__ double du[16][17], dl[16][17];
     // the level of this workgroup: the last one whose first slot is <= it
     const int bid = blockIdx.x;
@@ -1352,6 +1354,7 @@ __global__ __launch_bounds__(256) void k_panel_solve(double *__restrict__ slab, 
                                                      const int32_t *__restrict__ lvl,
                                                      const int32_t *__restrict__ trow_ptr,
                                                      const int32_t *__restrict__ trow_idx, int skip_blocked) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     extern __shared__ double xs_lds[];
     const LevelDev L = levels[lvl[blockIdx.z]];
     const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
@@ -1462,6 +1465,7 @@ __global__ __launch_bounds__(256) void k_panel_solve_pf(double *__restrict__ sla
                                                      const int32_t *__restrict__ lvl,
                                                      const int32_t *__restrict__ trow_ptr,
                                                      const int32_t *__restrict__ trow_idx, int skip_blocked) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     extern __shared__ double xs_lds[];
     const LevelDev L = levels[lvl[blockIdx.z]];
     const int kp = L.kp, kap = L.kappa, m = L.m, nt = kp >> 4;
@@ -1637,6 +1641,7 @@ __global__ __launch_bounds__(256) void k_panel_solve_pf(double *__restrict__ sla
 __global__ __launch_bounds__(64) void k_tri_binv(const double *__restrict__ tri, double *__restrict__ binv,
                                                  const LevelDev *__restrict__ levels,
                                                  const int32_t *__restrict__ lvl) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     const LevelDev L = levels[lvl[blockIdx.y]];
     if (L.offB < 0) return;
     const int kp = L.kp, nt = kp >> 4, nbk = (kp + kPanelBlk - 1) / kPanelBlk;
@@ -1695,6 +1700,7 @@ __global__ __launch_bounds__(256) void k_panel_blk(double *__restrict__ slab, co
                                                    const double *__restrict__ binv,
                                                    const LevelDev *__restrict__ levels,
                                                    const int32_t *__restrict__ lvl, int J, int rtiles_max) {
+    __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
     __shared__ double xs[32 * (kPanelBlk + 1)];
     const LevelDev L = levels[lvl[blockIdx.y]];
     if (L.offB < 0) return;

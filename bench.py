@@ -381,7 +381,9 @@ def rooflines(res, traffic_key):
         ach = fl / (kms * 1e-3) / 1e12
         out[k] = {"bound": bounds[k], "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                   "frac": ach / PEAK_FP64_TFLOPS, "traffic": stored_traffic(traffic_key, k),
-                  "avg_launch_us": kms * 1e3 / kn, "launches": kn, "algorithmic_flops_per_launch": fl / kn}
+                  "avg_launch_us": kms * 1e3 / kn, "launches": kn, "algorithmic_flops_per_launch": fl / kn,
+                  "timed_in": "per-kernel pass: one factor, serial schedule (no lookahead), HIP event pairs "
+                              "around each wave's run of launches of the class on the launch stream"}
     return out
 
 

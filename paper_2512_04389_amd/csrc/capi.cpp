@@ -587,7 +587,14 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
             SLU_BEGIN(SLU_KERNEL_PANEL);
             SLU_LAUNCH(slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             const bool blk = h->panel_blocked && w.max_kp >= slu::kPanelBlkKp;
-            SLU_LAUNCH(slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, blk ? 1 : 0, s));
+            // the tile-wise solve, unless every level of the wave takes the
+            // blocked one
+            bool tilewise = !blk;
+            for (int q = w.begin; q < w.end && !tilewise; ++q) {
+                const slu::LevelDev &L = an.levels[an.wave_levels[q]];
+                if (L.m > 0 && L.kp > 0 && L.offB < 0) tilewise = true;
+            }
+            if (tilewise) SLU_LAUNCH(slu::launch_panel_solve_wave(d, lv, nlev, w.max_m, w.max_kp, blk ? 1 : 0, s));
             if (blk) {
                 if (hip_failed(slu::launch_panel_blk_wave(d, lv, nlev, w.max_m, w.max_kp, s))) return SLU_ERR_HIP;
                 kt.launched(1 + (w.max_kp + slu::kPanelBlk - 1) / slu::kPanelBlk);

@@ -1730,12 +1730,14 @@ __global__ __launch_bounds__(256) void k_panel_blk(double *__restrict__ slab, co
             }
         }
     if (J >= 0 && wact) {
-        // K = 128 in four batches of eight 4-deep steps; the loads of the
-        // next batch are in flight while the current one's MFMAs run
+        // K = 128 in eight batches of four 4-deep steps; the loads of the
+        // next batch are in flight while the current one's MFMAs run (short
+        // batches keep the registers low enough for three waves per SIMD,
+        // whose interleaving hides more latency than a deeper prefetch)
         const int k0 = kPanelBlk * J;
         const bool rok0 = r0 + li < m, rok1 = r0 + 16 + li < m;
         const bool cok0 = cw + li < c0 + wb, cok1 = cw + 16 + li < c0 + wb;
-        constexpr int KB = 8, NB = kPanelBlk / 4 / KB;
+        constexpr int KB = 4, NB = kPanelBlk / 4 / KB;
         double ca[2][KB][2], cbv[2][KB][2];
         auto fetch = [&](int nb, double (&a)[KB][2], double (&bv)[KB][2]) {
 #pragma unroll

@@ -1638,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_panel_solve_pf(double *__restrict__ sla
 //     another of its workgroups reads.
 // Every product is an FP64 MFMA 16 x 16 x 4 chain; the same X T^{-1} as the
 // tile-by-tile solve, with the substitutions grouped into block inverses.
-__global__ __launch_bounds__(64) void k_tri_binv(const double *__restrict__ tri, double *__restrict__ binv,
+__global__ __launch_bounds__(64, 4) void k_tri_binv(const double *__restrict__ tri, double *__restrict__ binv,
                                                  const LevelDev *__restrict__ levels,
                                                  const int32_t *__restrict__ lvl) {
     __builtin_amdgcn_s_setprio(3);   // issue ahead of co-resident deferred Schur-update waves
@@ -1696,7 +1696,7 @@ __global__ __launch_bounds__(64) void k_tri_binv(const double *__restrict__ tri,
     }
 }
 
-__global__ __launch_bounds__(256) void k_panel_blk(double *__restrict__ slab, const double *__restrict__ tri,
+__global__ __launch_bounds__(256, 4) void k_panel_blk(double *__restrict__ slab, const double *__restrict__ tri,
                                                    const double *__restrict__ binv,
                                                    const LevelDev *__restrict__ levels,
                                                    const int32_t *__restrict__ lvl, int J, int rtiles_max) {

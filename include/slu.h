@@ -292,13 +292,17 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
 
 /* Tiled diagonal solves: in slu_solve, slu_solve_transpose and the solves
  * inside slu_solve_refined, a wave whose largest diagonal block has at least
- * min_rows rows (default 256; 0: never), whose blocks are dense (S fills at
- * least half of every block's lower triangle) and were factored by the
- * 32 x 32 tiled GETRF solves its diagonal blocks tile by tile across the GPU
- * with the inverted diagonal tiles the factorization kept (one launch per
- * tile step; one workgroup per block otherwise).  Same results up to
- * rounding.  SLU_ERR_ARG for a negative min_rows. */
-int slu_set_solve_tiled(slu_handle *h, int min_rows);
+ * min_rows rows (default 256; 0: never), whose blocks were factored by the
+ * 32 x 32 tiled GETRF and are either dense (S fills at least half of every
+ * block's lower triangle) or, in sweeps of 4 or more right-hand sides, all
+ * at least min_sparse_rows rows (default 640; 0: dense blocks only) solves
+ * its diagonal blocks tile by tile across the
+ * GPU with the inverted diagonal tiles the factorization kept (one launch per
+ * tile step, b / 32 + 1 steps); otherwise one workgroup per block walks its
+ * column chunks (b / 16 dependent steps, cheaper for sparse blocks of a few
+ * hundred rows).  Same results up to rounding.  SLU_ERR_ARG for a negative
+ * argument. */
+int slu_set_solve_tiled(slu_handle *h, int min_rows, int min_sparse_rows);
 
 /* Lookahead of the Schur updates (Algorithm 1's SSSSM; the level order of
  * Section 3.2): with enable = 1 the updates of a wave whose

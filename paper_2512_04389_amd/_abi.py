@@ -145,7 +145,7 @@ def _load():
         "slu_set_getrf_tile": (i32, [hp, ctypes.c_int]),
         "slu_set_panel_blocked": (i32, [hp, ctypes.c_int]),
         "slu_set_lookahead": (i32, [hp, ctypes.c_int, ctypes.c_int]),
-        "slu_set_solve_tiled": (i32, [hp, ctypes.c_int]),
+        "slu_set_solve_tiled": (i32, [hp, ctypes.c_int, ctypes.c_int]),
         "slu_autotune": (i32, [hp, p, i32, p, i32, ctypes.POINTER(ctypes.c_int), p]),
         "slu_last_hip_error": (i32, []),
         "slu_set_host_threads": (i32, [i32]),

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -50,6 +51,7 @@ struct slu_handle {
     // tiled GETRF (0: never); wave_tinv: per wave, the last factor kept the
     // inverted diagonal tiles
     int solve_tiled_rows = 256;
+    int solve_tiled_sparse_rows = 640;   // ... and, for blocks under half dense, at least this many
     std::vector<char> wave_tinv;
     // Schur updates of a wave (of one round) that reach only later waves run
     // on a second stream (default priority) while the next wave factors its
@@ -148,10 +150,15 @@ hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s
 // threshold and its blocks are dense (at least half of every block's lower
 // triangle in S: the one-workgroup solve walks only the coupled rows of
 // sparse blocks and wins there).
-bool tiled_solve(const slu_handle *h, size_t wi) {
+bool tiled_solve(const slu_handle *h, size_t wi, int nc) {
     const slu::WaveInfo &w = h->an.waves[wi];
+    // dense blocks, or, for sweeps of several right-hand sides (whose cost
+    // grows the one-workgroup walk of the column chunks, a chain of b / 16
+    // steps, more than the b / 32 + 1 chip-wide tile steps), blocks of
+    // min_sparse_rows rows or more whatever their density
+    const bool worth = w.min_dense_pct >= 50 || (nc >= 4 && w.min_b >= h->solve_tiled_sparse_rows);
     return h->solve_tiled_rows > 0 && wi < h->wave_tinv.size() && h->wave_tinv[wi] && w.min_b > 16 &&
-           w.max_b >= h->solve_tiled_rows && w.min_dense_pct >= 50 && w.end - w.begin <= 65535;
+           w.max_b >= h->solve_tiled_rows && worth && w.end - w.begin <= 65535;
 }
 
 int solve_check(const slu_handle *h, const double *B, const double *X, int64_t nrhs, int64_t ld) {
@@ -180,7 +187,7 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
         for (size_t wi = 0; wi < an.waves.size(); ++wi) {
             const slu::WaveInfo &w = an.waves[wi];
             const int nlev = w.end - w.begin;
-            if (tiled_solve(h, wi)) {
+            if (tiled_solve(h, wi, nc)) {
                 if (hip_failed(slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
                     return SLU_ERR_HIP;
             } else if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans,
@@ -206,7 +213,7 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
             }
             if (hip_failed(slu::launch_bwd_update(d, d.wave_levels + w.begin, nlev, max_kappa, nc, trans, s)))
                 return SLU_ERR_HIP;
-            if (tiled_solve(h, wi)) {
+            if (tiled_solve(h, wi, nc)) {
                 if (hip_failed(
                         slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
                     return SLU_ERR_HIP;
@@ -870,9 +877,10 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
     return rc;
 }
 
-int slu_set_solve_tiled(slu_handle *h, int min_rows) {
-    if (!h || min_rows < 0) return SLU_ERR_ARG;
+int slu_set_solve_tiled(slu_handle *h, int min_rows, int min_sparse_rows) {
+    if (!h || min_rows < 0 || min_sparse_rows < 0) return SLU_ERR_ARG;
     h->solve_tiled_rows = min_rows;
+    h->solve_tiled_sparse_rows = min_sparse_rows == 0 ? INT32_MAX : min_sparse_rows;
     return SLU_OK;
 }
 

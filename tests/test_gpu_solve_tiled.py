@@ -35,6 +35,10 @@ CASES = {
     "bbd-6000-regular-700": lambda: (synth.bbd_circuit(n=6000, nblocks=4, border=300, border_nnz=20000, seed=9),
                                      dict(blocking="regular", block_size=700)),
     "bbd-6000-irregular": lambda: (synth.bbd_circuit(n=6000, nblocks=4, border=300, border_nnz=20000, seed=9), {}),
+    # sparse 700-row blocks: tiled only when sparse blocks are allowed
+    "convdiff-14-regular-700": lambda: (synth.convection_diffusion_3d(14),
+                                        dict(ordering="grid_nd", grid_dims=(14, 14, 14), blocking="regular",
+                                             block_size=700)),
     "convdiff-14-regular-300": lambda: (synth.convection_diffusion_3d(14),
                                         dict(ordering="grid_nd", grid_dims=(14, 14, 14), blocking="regular",
                                              block_size=300)),
@@ -54,7 +58,8 @@ def test_tiled_solve_matches(case):
     B = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     out = {}
     for rows in (1, 0):
-        h.set_solve_tiled(rows)
+        # rows = 1: every wave factored by the tiled GETRF, any density
+        h.set_solve_tiled(rows, 1)
         for trans in (False, True):
             X = (h.solve_transpose(B) if trans else h.solve(B)).cpu().numpy()
             eta = metrics.backward_error(n, rp, ci, v, X, b, transpose=trans)
@@ -63,7 +68,7 @@ def test_tiled_solve_matches(case):
     for trans in (False, True):
         d = np.max(np.abs(out[(1, trans)] - out[(0, trans)])) / np.max(np.abs(out[(0, trans)]))
         assert d < 1e-10, (trans, d)
-    h.set_solve_tiled(1)
+    h.set_solve_tiled(1, 1)
     Xn = h.solve_noalloc(B).cpu().numpy()
     np.testing.assert_array_equal(Xn, out[(1, False)])
     h.set_precision("fp32")
@@ -71,4 +76,5 @@ def test_tiled_solve_matches(case):
     Xr, its, eta_dev, conv = h.solve_refined(vals, B)
     eta = metrics.backward_error(n, rp, ci, v, Xr.cpu().numpy(), b)
     assert conv and np.all(eta <= ETA_MAX), eta
-    assert slu.lib.slu_set_solve_tiled(h._h, -1) == slu._abi.SLU_ERR_ARG
+    assert slu.lib.slu_set_solve_tiled(h._h, -1, 640) == slu._abi.SLU_ERR_ARG
+    assert slu.lib.slu_set_solve_tiled(h._h, 256, -1) == slu._abi.SLU_ERR_ARG

@@ -188,7 +188,9 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
             const slu::WaveInfo &w = an.waves[wi];
             const int nlev = w.end - w.begin;
             if (tiled_solve(h, wi, nc)) {
-                if (hip_failed(slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, s)))
+                const slu::LevelDev *one = nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr;
+                if (hip_failed(
+                        slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, one, s)))
                     return SLU_ERR_HIP;
             } else if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans,
                                                               s))) {
@@ -215,7 +217,8 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
                 return SLU_ERR_HIP;
             if (tiled_solve(h, wi, nc)) {
                 if (hip_failed(
-                        slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans, s)))
+                        slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans,
+                                                    nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr, s)))
                     return SLU_ERR_HIP;
             } else if (hip_failed(slu::launch_solve_diag_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc,
                                                               trans, s))) {

@@ -2462,12 +2462,21 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // own rows.  M_t is iL_t, iU_t^T, iU_t or iL_t^T; A_rt is the block's tile
 // (r, t), transposed for the transposed solve.  The right-hand sides of a
 // 32-row tile are the 16 columns of 16 x 16 x 4 FP64 MFMA products (nc <= 16).
-__global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ slab, const double *__restrict__ work,
-                                                   const LevelDev *__restrict__ levels,
-                                                   const int32_t *__restrict__ lvl, int u, int fwd, int trans,
-                                                   double *__restrict__ Wx, int64_t n, int nc) {
-    const LevelDev L = levels[lvl[blockIdx.y]];
-    const int b = L.b, nt = (b + 31) >> 5;
+template <bool ONE>
+__global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD1, int64_t offW1,
+                                                   const double *__restrict__ slab, const double *__restrict__ work,
+                                                   double *__restrict__ Wx, int64_t n, int u, int fwd, int trans,
+                                                   int nc, const LevelDev *__restrict__ levels,
+                                                   const int32_t *__restrict__ lvl) {
+    int b, r0;
+    int64_t offD, offW;
+    if constexpr (ONE) {
+        b = b1, r0 = r01, offD = offD1, offW = offW1;
+    } else {
+        const LevelDev &L = levels[lvl[blockIdx.y]];
+        b = L.b, r0 = L.r0, offD = L.offD, offW = L.offW;
+    }
+    const int nt = (b + 31) >> 5;
     if (u > nt) return;
     const int q = blockIdx.x;
     // step u handles tile t (solved now) and finalizes tile tp (solved in u - 1)
@@ -2482,11 +2491,16 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
     else
         r = fwd ? t + 1 + (q - q0) : t - 1 - (q - q0);
     if (r < 0 || r >= nt) return;
-    const double *__restrict__ D = slab + L.offD;
-    const double *__restrict__ Inv = work + L.offW + 128 * (size_t)b;
+    const double *__restrict__ D = slab + offD;
+    const double *__restrict__ Inv = work + offW + 128 * (size_t)b;
     const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
     const bool rhs_ok = li < nc;
-    double *__restrict__ Xc = Wx + (size_t)(rhs_ok ? li : 0) * n + L.r0;   // this lane's right-hand side
+    double *__restrict__ Xc = Wx + (size_t)(rhs_ok ? li : 0) * n + r0;   // this lane's right-hand side
+    // Loads are unconditional from clamped addresses, so that they all go out
+    // together.  Rows past b read an in-range value: the inverted tiles are
+    // the identity there and zero beside it, so such a value only reaches
+    // rows past b of x, which are never stored and meet only zeroed entries
+    // of A below (entries past b are multiplied by 0).
     const bool use_l = (fwd != 0) == (trans == 0);   // M and A from L (else from U)
     // M_s (32 x 32 inverses of tile s, iL row-major, iU column-major):
     // element (i, k) of the operator applied, i.e. iL / iU, transposed for
@@ -2504,8 +2518,7 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
         for (int hk = 0; hk < 2; ++hk)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int row = 32 * s2 + 16 * hk + 4 * kk + g;
-                bb[hk][kk] = (rhs_ok && row < b) ? Xc[row] : 0.0;
+                bb[hk][kk] = Xc[min(32 * s2 + 16 * hk + 4 * kk + g, b - 1)];
             }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -2543,8 +2556,7 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int row = 32 * r + 16 * h + g + 4 * e;
-            acc[h][e] = (rhs_ok && row < b) ? Xc[row] : 0.0;
+            acc[h][e] = Xc[min(32 * r + 16 * h + g + 4 * e, b - 1)];
         }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -2554,8 +2566,8 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int ck = 32 * t + 16 * hk + 4 * kk + g;
-                double a = 0.0;
-                if (ri < b && ck < b) a = trans ? D[(size_t)ri * b + ck] : D[(size_t)ck * b + ri];
+                const size_t ric = (size_t)min(ri, b - 1), ckc = (size_t)min(ck, b - 1);
+                const double a = (trans ? D[ric * b + ckc] : D[ckc * b + ric]) * ((ri < b && ck < b) ? 1.0 : 0.0);
                 acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, x[hk][kk], acc[h], 0, 0, 0);
             }
     }
@@ -2571,15 +2583,20 @@ __global__ __launch_bounds__(64) void k_solve_tile(const double *__restrict__ sl
 }
 
 hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
-                                  int trans, hipStream_t s) {
+                                  int trans, const LevelDev *one, hipStream_t s) {
     if (nlev <= 0 || nlev > 65535) return hipErrorInvalidValue;
     const int nt = (max_b + 31) / 32;
     for (int u = 0; u <= nt; ++u) {
         // rows handled in step u: the finalized tile plus the tiles it updates
         const unsigned gx = (unsigned)(u == 0 ? nt - 1 : (nt - u > 1 ? nt - u : 1));
         if (gx == 0) continue;
-        hipLaunchKernelGGL(k_solve_tile, dim3(gx, (unsigned)nlev), dim3(64), 0, s, d.slab, d.tgetrf, d.levels, lvl,
-                           u, fwd ? 1 : 0, trans, d.scratch, d.n, nc);
+        if (nlev == 1 && one)
+            hipLaunchKernelGGL(k_solve_tile<true>, dim3(gx, 1), dim3(64), 0, s, one->b, one->r0, one->offD, one->offW,
+                               d.slab, d.tgetrf, d.scratch, d.n, u, fwd ? 1 : 0, trans, nc, d.levels, lvl);
+        else
+            hipLaunchKernelGGL(k_solve_tile<false>, dim3(gx, (unsigned)nlev), dim3(64), 0, s, 0, 0, (int64_t)0,
+                               (int64_t)0, d.slab, d.tgetrf, d.scratch, d.n, u, fwd ? 1 : 0, trans, nc, d.levels,
+                               lvl);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

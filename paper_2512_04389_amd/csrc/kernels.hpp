@@ -103,7 +103,7 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // Tiled diagonal solves of a wave factored by the 32 x 32 tiled GETRF (its
 // inverted diagonal tiles kept): one launch per tile step, max_b + 31 / 32 + 1.
 hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_b, bool fwd, int nc,
-                                  int trans, hipStream_t s);
+                                  int trans, const LevelDev *one, hipStream_t s);
 // Forward updates of the nlev levels in lvl (levels whose target rows are
 // disjoint: one Schur-update round); max_m is their largest m.
 hipError_t launch_fwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int nc, int trans,

@@ -2605,10 +2605,12 @@ hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev
 
 // W[rows_i[a]] -= X[a, :] . W[r0 + K_i]   (X = P_i, or Qt_i when transposed)
 // for the levels of one Schur-update round, whose target rows are disjoint:
-// blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) its 64-row
-// tiles.  A workgroup takes 64 rows (one per lane); its four waves split the
-// inner index, whose W values are staged in LDS 256 at a time; the four
-// partial sums are added in LDS in a fixed order.
+// blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) its 32-row
+// tiles.  The right-hand sides are the 16 columns of FP64 MFMA 16 x 16 x 4
+// products (columns past nc are zero); the four waves split the inner index
+// in interleaved 4-deep steps, with its W values staged in LDS 256 at a time
+// (column-major, padded against bank conflicts); the four partial sums are
+// added in LDS in a fixed order.
 constexpr int kUpdSlice = 256;
 
 __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ slab,
@@ -2617,54 +2619,53 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
                                                     const int32_t *__restrict__ Kidx,
                                                     const int32_t *__restrict__ Ridx, double *__restrict__ W,
                                                     int64_t n, int nc, int trans) {
-    __shared__ double xk[kUpdSlice * kSolveCols];
-    __shared__ double part[4][kSolveCols][64];
+    constexpr int XL = kUpdSlice + 1;
+    __shared__ double xk[16 * XL];               // [c][t]
+    __shared__ double part[4][2][4][64];         // [wave][h][r][lane]
     const LevelDev L = levels[lvl[blockIdx.x]];
     const int m = L.m, kap = L.kappa;
     const double *__restrict__ X = slab + (trans ? L.offQ : L.offP);
     const int32_t *__restrict__ K = Kidx + L.Koff;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int tile = blockIdx.y; tile * 64 < m; tile += gridDim.y) {
-        const int a = tile * 64 + lane;
-        const int ac = min(a, m - 1);
-        double acc[kSolveCols];
-#pragma unroll
-        for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+    for (int e = tid; e < 16 * XL; e += 256) xk[e] = 0.0;   // columns past nc stay zero
+    for (int tile = blockIdx.y; tile * 32 < m; tile += gridDim.y) {
+        const int row0 = tile * 32;
+        const size_t ra0 = (size_t)min(row0 + li, m - 1), ra1 = (size_t)min(row0 + 16 + li, m - 1);
+        double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
         for (int t0 = 0; t0 < kap; t0 += kUpdSlice) {
             const int nt = min(kUpdSlice, kap - t0);
             __syncthreads();
-            for (int e = tid; e < nt * nc; e += 256) {
-                const int t = e / nc, c = e - t * nc;
-                xk[e] = W[L.r0 + K[t0 + t] + (size_t)c * n];
+            for (int e = tid; e < nc * kUpdSlice; e += 256) {
+                const int c = e / kUpdSlice, t = e - c * kUpdSlice;
+                if (t < nt) xk[c * XL + t] = W[L.r0 + K[t0 + t] + (size_t)c * n];
             }
             __syncthreads();
-            // this wave's inner indices t = wave + 4 u, eight loads in flight
-            for (int u0 = wave; u0 < nt; u0 += 32) {
-                double pv[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) pv[q] = X[ac + (size_t)(t0 + min(u0 + 4 * q, nt - 1)) * m];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int t = u0 + 4 * q;
-                    if (t < nt) {
-#pragma unroll
-                        for (int c = 0; c < kSolveCols; ++c)
-                            if (c < nc) acc[c] += pv[q] * xk[t * nc + c];
-                    }
-                }
+            // step j: inner index t = 16 j + 4 wave + g in lane group g
+            const int nst = (nt + 15) >> 4;
+            for (int j = 0; j < nst; ++j) {
+                const int t = 16 * j + 4 * wave + g;
+                const bool tok = t < nt;
+                const size_t tc = (size_t)(t0 + min(t, nt - 1));
+                const double msk = tok ? 1.0 : 0.0;
+                const double a0 = X[tc * m + ra0] * msk, a1 = X[tc * m + ra1] * msk;
+                const double bv = tok ? xk[li * XL + t] : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1, 0, 0, 0);
             }
         }
-        __syncthreads();
+        // acc_h[r] of lane (li, g): row 16 h + g + 4 r of the tile, column li
 #pragma unroll
-        for (int c = 0; c < kSolveCols; ++c)
-            if (c < nc) part[wave][c][lane] = acc[c];
+        for (int r = 0; r < 4; ++r) {
+            part[wave][0][r][lane] = acc0[r];
+            part[wave][1][r][lane] = acc1[r];
+        }
         __syncthreads();
-        for (int e = tid; e < 64 * nc; e += 256) {
-            const int c = e >> 6, r = e & 63;
-            const int row = tile * 64 + r;
-            if (row < m) {
-                const double v = (part[0][c][r] + part[1][c][r]) + (part[2][c][r] + part[3][c][r]);
-                W[Ridx[L.Roff + row] + (size_t)c * n] -= v;
+        for (int e = tid; e < 32 * nc; e += 256) {
+            const int c = e >> 5, row = e & 31;
+            const int h = row >> 4, rr = row & 15, pl = c + 16 * (rr & 3), pr = rr >> 2;
+            if (row0 + row < m) {
+                const double v = (part[0][h][pr][pl] + part[1][h][pr][pl]) + (part[2][h][pr][pl] + part[3][h][pr][pl]);
+                W[Ridx[L.Roff + row0 + row] + (size_t)c * n] -= v;
             }
         }
     }
@@ -2697,7 +2698,7 @@ __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ sl
 hipError_t launch_fwd_update(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int nc, int trans,
                              hipStream_t s) {
     if (nlev <= 0 || max_m <= 0) return hipSuccess;
-    const int64_t tiles = ((int64_t)max_m + 63) / 64;
+    const int64_t tiles = ((int64_t)max_m + 31) / 32;
     hipLaunchKernelGGL(k_fwd_update, dim3((unsigned)nlev, (unsigned)std::min<int64_t>(tiles, 65535)), dim3(256), 0,
                        s, d.slab, d.levels, lvl, d.K_idx, d.R_idx, d.scratch, d.n, nc, trans);
     return hipGetLastError();

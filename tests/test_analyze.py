@@ -194,3 +194,25 @@ def test_analysis_independent_of_host_threads():
     assert i1 == i4 and w1 == w4
     assert np.array_equal(b1, b4) and np.array_equal(c1, c4) and np.array_equal(r1, r4)
     assert _abi.lib.slu_set_host_threads(-1) == _abi.SLU_ERR_ARG
+
+
+def test_launch_setting_arguments():
+    """The launch-shape settings check their arguments on an analysed handle
+    (no workspace, no GPU needed)."""
+    import numpy as np
+    import paper_2512_04389_amd as slu
+    n, rp, ci, _ = synth.laplacian_2d(12)
+    h = slu.SparseLU(n, rp, ci)
+    lib, E = slu.lib, _abi.SLU_ERR_ARG
+    assert lib.slu_set_lookahead(h._h, 1, 512) == _abi.SLU_OK
+    assert lib.slu_set_lookahead(h._h, 0, 0) == _abi.SLU_OK
+    for en, g in ((2, 512), (-1, 512), (1, 100), (1, -8)):
+        assert lib.slu_set_lookahead(h._h, en, g) == E
+    assert lib.slu_set_solve_tiled(h._h, 256, 640) == _abi.SLU_OK
+    assert lib.slu_set_solve_tiled(h._h, 0, 0) == _abi.SLU_OK
+    assert lib.slu_set_solve_tiled(h._h, -1, 640) == E
+    assert lib.slu_set_solve_tiled(h._h, 256, -1) == E
+    assert lib.slu_set_panel_blocked(h._h, 2) == E
+    assert lib.slu_set_getrf_tile(h._h, 24) == E
+    assert lib.slu_set_getrf_tiled(h._h, -1) == E
+    h.close()

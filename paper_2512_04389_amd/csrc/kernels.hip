@@ -2547,17 +2547,10 @@ __global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD
         return;
     }
     if (u >= nt) return;
-    double4_t x[2];
-    solve_tile(t, x);
     // b_r -= A_rt x_t: A_rt(i, k) = D(32 r + i, 32 t + k), or D(32 t + k, 32 r + i)
-    // for the transposed solve
-    double4_t acc[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            acc[h][e] = Xc[min(32 * r + 16 * h + g + 4 * e, b - 1)];
-        }
+    // for the transposed solve.  Its operands (and b_r) are loaded before
+    // tile t is solved, so that both memory round trips overlap.
+    double av[2][2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int ri = 32 * r + 16 * h + li;
@@ -2567,10 +2560,23 @@ __global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD
             for (int kk = 0; kk < 4; ++kk) {
                 const int ck = 32 * t + 16 * hk + 4 * kk + g;
                 const size_t ric = (size_t)min(ri, b - 1), ckc = (size_t)min(ck, b - 1);
-                const double a = (trans ? D[ric * b + ckc] : D[ckc * b + ric]) * ((ri < b && ck < b) ? 1.0 : 0.0);
-                acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, x[hk][kk], acc[h], 0, 0, 0);
+                av[h][hk][kk] = (trans ? D[ric * b + ckc] : D[ckc * b + ric]) * ((ri < b && ck < b) ? -1.0 : 0.0);
             }
     }
+    double4_t acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[h][e] = Xc[min(32 * r + 16 * h + g + 4 * e, b - 1)];
+    double4_t x[2];
+    solve_tile(t, x);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][hk][kk], x[hk][kk], acc[h], 0, 0, 0);
     if (rhs_ok) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)

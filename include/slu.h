@@ -294,9 +294,8 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
  * inside slu_solve_refined, a wave whose largest diagonal block has at least
  * min_rows rows (default 256; 0: never), whose blocks were factored by the
  * 32 x 32 tiled GETRF and are either dense (S fills at least half of every
- * block's lower triangle) or, in sweeps of 4 or more right-hand sides, all
- * at least min_sparse_rows rows (default 640; 0: dense blocks only) solves
- * its diagonal blocks tile by tile across the
+ * block's lower triangle) or all at least min_sparse_rows rows (default 640;
+ * 0: dense blocks only) solves its diagonal blocks tile by tile across the
  * GPU with the inverted diagonal tiles the factorization kept (one launch per
  * tile step, b / 32 + 1 steps); otherwise one workgroup per block walks its
  * column chunks (b / 16 dependent steps, cheaper for sparse blocks of a few

@@ -150,13 +150,13 @@ hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s
 // threshold and its blocks are dense (at least half of every block's lower
 // triangle in S: the one-workgroup solve walks only the coupled rows of
 // sparse blocks and wins there).
-bool tiled_solve(const slu_handle *h, size_t wi, int nc) {
+bool tiled_solve(const slu_handle *h, size_t wi) {
     const slu::WaveInfo &w = h->an.waves[wi];
-    // dense blocks, or, for sweeps of several right-hand sides (whose cost
-    // grows the one-workgroup walk of the column chunks, a chain of b / 16
-    // steps, more than the b / 32 + 1 chip-wide tile steps), blocks of
-    // min_sparse_rows rows or more whatever their density
-    const bool worth = w.min_dense_pct >= 50 || (nc >= 4 && w.min_b >= h->solve_tiled_sparse_rows);
+    // dense blocks, or blocks large enough (min_sparse_rows) that the
+    // one-workgroup walk of their column chunks, a chain of b / 16 steps,
+    // takes longer than the b / 32 + 1 chip-wide tile steps whatever their
+    // density
+    const bool worth = w.min_dense_pct >= 50 || w.min_b >= h->solve_tiled_sparse_rows;
     return h->solve_tiled_rows > 0 && wi < h->wave_tinv.size() && h->wave_tinv[wi] && w.min_b > 16 &&
            w.max_b >= h->solve_tiled_rows && worth && w.end - w.begin <= 65535;
 }
@@ -187,7 +187,7 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
         for (size_t wi = 0; wi < an.waves.size(); ++wi) {
             const slu::WaveInfo &w = an.waves[wi];
             const int nlev = w.end - w.begin;
-            if (tiled_solve(h, wi, nc)) {
+            if (tiled_solve(h, wi)) {
                 const slu::LevelDev *one = nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr;
                 if (hip_failed(
                         slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, true, nc, trans, one, s)))
@@ -215,7 +215,7 @@ int solve_sweeps(slu_handle *h, const slu::DevPlan &d, int cols, const double *B
             }
             if (hip_failed(slu::launch_bwd_update(d, d.wave_levels + w.begin, nlev, max_kappa, nc, trans, s)))
                 return SLU_ERR_HIP;
-            if (tiled_solve(h, wi, nc)) {
+            if (tiled_solve(h, wi)) {
                 if (hip_failed(
                         slu::launch_solve_tile_wave(d, d.wave_levels + w.begin, nlev, w.max_b, false, nc, trans,
                                                     nlev == 1 ? &an.levels[an.wave_levels[w.begin]] : nullptr, s)))

@@ -306,11 +306,12 @@ int slu_set_solve_tiled(slu_handle *h, int min_rows, int min_sparse_rows);
 /* Lookahead of the Schur updates (Algorithm 1's SSSSM; the level order of
  * Section 3.2): with enable = 1 the updates of a wave whose
  * levels have pairwise disjoint targets (one launch round) are split by
- * target.  The updates of the next wave's diagonal blocks and panels run on
- * the factor's stream as before; the updates that reach only later waves run
- * on a second stream of the library's own (default priority) while the next
- * wave factors its diagonal blocks and solves its panels, and the next
- * updates on the factor's stream wait for them.  Waves of several rounds run
+ * target.  The updates of the next wave's diagonal blocks run on the
+ * factor's stream as before; on a second stream of the library's own
+ * (default priority) follow the updates of the next wave's panels (which its
+ * panel solve waits for) and then those that reach only later waves (which
+ * the next updates on the factor's stream wait for), while the next wave
+ * factors its diagonal blocks and solves its panels.  Waves of several rounds run
  * their updates on the factor's stream.  max_groups (a multiple of 8; 0: one
  * workgroup per tile) caps the workgroups of a deferred launch, which then
  * walk its tiles, so that they leave room on every CU for the factor's

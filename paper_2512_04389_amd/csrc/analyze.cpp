@@ -876,24 +876,26 @@ int analyze(int64_t n, const int64_t *rowptr, const int32_t *colidx, const slu_o
                 int32_t mmax = 0;
                 for (int32_t i : r) mmax = std::max(mmax, an.levels[i].m);
                 ri.tile = mmax < kSsssmSmallM ? 32 : kSsssmTile;
-                int64_t t = 0, tc = 0, tr = 0;
+                int64_t t = 0, tc = 0, tr = 0, td = 0, tq = 0;
                 for (int32_t i : r) {
                     LevelDev &L = an.levels[i];
                     const int64_t nt = ((int64_t)L.m + ri.tile - 1) / ri.tile;
                     const int64_t nc = std::min<int64_t>(nt, ((int64_t)crit_rows[i] + ri.tile - 1) / ri.tile);
                     L.sscrit = (int32_t)nc;
                     an.round_levels.push_back(i);
-                    an.round_tiles.push_back(t);
-                    an.round_tiles.push_back(tc);
-                    an.round_tiles.push_back(tr);
+                    for (int64_t v : {t, tc, tr, td, tq}) an.round_tiles.push_back(v);
                     t += nt * nt;
                     tr += (nt - nc) * (nt - nc);
                     tc += nt * nt - (nt - nc) * (nt - nc);
+                    td += nc * nc;
+                    tq += 2 * nc * (nt - nc);
                 }
                 ri.end = (int32_t)an.round_levels.size();
                 ri.tiles = t;
                 ri.tiles_c = tc;
                 ri.tiles_r = tr;
+                ri.tiles_d = td;
+                ri.tiles_pq = tq;
                 if (t >= ((int64_t)1 << 31)) return SLU_ERR_LIMIT;
                 an.rounds.push_back(ri);
             }

@@ -69,6 +69,8 @@ struct RoundInfo {
     int32_t begin, end;         // range in round_levels
     int64_t tiles;              // SSSSM workgroups of the round
     int64_t tiles_c, tiles_r;   // of which update the next wave / only later waves
+    int64_t tiles_d, tiles_pq;  // the next-wave tiles: the square of its first rows
+                                // (its diagonal blocks) / the two bands beside it
     int32_t tile, pad;          // tile edge (64, or 32 when every level is small)
 };
 
@@ -130,8 +132,9 @@ struct Analysis {
     std::vector<int32_t> wave_levels;
     std::vector<RoundInfo> rounds;
     std::vector<int32_t> round_levels;   // levels of every round, consecutive
-    // first SSSSM workgroup of each level within its round, three per level:
-    // counting all its tiles, the tiles that update the next wave, the rest
+    // first SSSSM workgroup of each level within its round, five per level:
+    // counting all its tiles, the tiles that update the next wave, the rest,
+    // the next wave's square and its two bands (see k_ssssm)
     std::vector<int64_t> round_tiles;
     std::vector<int32_t> tslot_off;      // per wave_levels entry: first triangle-gather workgroup of the level in its wave
     std::vector<int32_t> trow_ptr;   // nonzero tile lists of the coupled triangles

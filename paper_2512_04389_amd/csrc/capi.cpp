@@ -61,7 +61,7 @@ struct slu_handle {
     bool lookahead = false;
     int la_groups = 512;        // workgroups of a deferred update launch (0: one per tile)
     hipStream_t la_stream = nullptr;
-    hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_rest = nullptr, ev_pq = nullptr;
 };
 
 namespace {
@@ -529,11 +529,16 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
             return SLU_ERR_HIP;
         if (!h->ev_rest && hip_failed(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming)))
             return SLU_ERR_HIP;
+        if (!h->ev_pq && hip_failed(hipEventCreateWithFlags(&h->ev_pq, hipEventDisableTiming)))
+            return SLU_ERR_HIP;
     }
     // wave whose deferred updates the factor's stream has not waited for yet
     // (-1: none); they reach waves two or more later, so wave wi waits for
     // them before its first launch at the latest
     int64_t rest_wave = -1;
+    // wave whose updates of the next wave's panels run on the second stream
+    // and have not been waited for (the next wave's panel solve waits)
+    int64_t pq_wave = -1;
     for (size_t wi = 0; wi < an.waves.size(); ++wi) {
         const slu::WaveInfo &w = an.waves[wi];
         const int nlev = w.end - w.begin;
@@ -541,6 +546,7 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         if (rest_wave >= 0 && rest_wave + 2 <= (int64_t)wi) {
             if (hip_failed(hipStreamWaitEvent(s, h->ev_rest, 0))) return SLU_ERR_HIP;
             rest_wave = -1;
+            pq_wave = -1;
         }
         SLU_BEGIN(SLU_KERNEL_GETRF);
         // the tiled GETRF when selected, and for waves whose chunked GETRF
@@ -595,6 +601,10 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
         SLU_END();
         if (w.max_m > 0 && w.max_kp > 0) {
             SLU_BEGIN(SLU_KERNEL_PANEL);
+            if (pq_wave >= 0) {
+                if (hip_failed(hipStreamWaitEvent(s, h->ev_pq, 0))) return SLU_ERR_HIP;
+                pq_wave = -1;
+            }
             SLU_LAUNCH(slu::launch_tri_gather_wave(d, lv, d.tslot_off + w.begin, nlev, w.tslots, s));
             const bool blk = h->panel_blocked && w.max_kp >= slu::kPanelBlkKp;
             // the tile-wise solve, unless every level of the wave takes the
@@ -622,24 +632,34 @@ static int enqueue_factor(slu_handle *h, const double *values, hipStream_t s, Ke
                 // share targets, so a later round's updates must not run
                 // beside an earlier round's deferred ones
                 const bool split = w.round_end - w.round_begin == 1;
-                const int64_t rest = split ? an.rounds[w.round_begin].tiles_r : 0;
                 // the updates on this stream come after the previous wave's
                 // deferred updates (they may share targets)
                 if (rest_wave >= 0) {
                     if (hip_failed(hipStreamWaitEvent(s, h->ev_rest, 0))) return SLU_ERR_HIP;
                     rest_wave = -1;
+                    pq_wave = -1;
                 }
-                for (int r = w.round_begin; r < w.round_end; ++r)
-                    SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], f32, split ? 1 : 0, 0, s));
-                // the deferred updates start once the next wave's are done,
-                // so they fill the next wave's diagonal and panel phase
-                if (rest > 0 && hip_failed(hipEventRecord(h->ev_panel, s))) return SLU_ERR_HIP;
-                if (rest > 0) {
-                    hipStream_t b = h->la_stream;
-                    if (hip_failed(hipStreamWaitEvent(b, h->ev_panel, 0))) return SLU_ERR_HIP;
-                    SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[w.round_begin], f32, 2, h->la_groups, b));
-                    if (hip_failed(hipEventRecord(h->ev_rest, b))) return SLU_ERR_HIP;
-                    rest_wave = (int64_t)wi;
+                if (!split) {
+                    for (int r = w.round_begin; r < w.round_end; ++r)
+                        SLU_LAUNCH(slu::launch_ssssm_round(d, an.rounds[r], f32, 0, 0, s));
+                } else {
+                    const slu::RoundInfo &ri = an.rounds[w.round_begin];
+                    // the next wave's diagonal blocks here; its panels and the
+                    // later waves' targets on the second stream, beside the
+                    // next wave's GETRF (panels first, at full width; the
+                    // rest in a capped grid)
+                    SLU_LAUNCH(slu::launch_ssssm_round(d, ri, f32, 3, 0, s));
+                    if (ri.tiles_pq > 0 || ri.tiles_r > 0) {
+                        hipStream_t b = h->la_stream;
+                        if (hip_failed(hipEventRecord(h->ev_panel, s))) return SLU_ERR_HIP;
+                        if (hip_failed(hipStreamWaitEvent(b, h->ev_panel, 0))) return SLU_ERR_HIP;
+                        SLU_LAUNCH(slu::launch_ssssm_round(d, ri, f32, 4, 0, b));
+                        if (hip_failed(hipEventRecord(h->ev_pq, b))) return SLU_ERR_HIP;
+                        SLU_LAUNCH(slu::launch_ssssm_round(d, ri, f32, 2, h->la_groups, b));
+                        if (hip_failed(hipEventRecord(h->ev_rest, b))) return SLU_ERR_HIP;
+                        rest_wave = (int64_t)wi;
+                        pq_wave = (int64_t)wi;
+                    }
                 }
             }
             SLU_END();
@@ -1105,6 +1125,7 @@ void slu_free(slu_handle *h) {
     if (h->la_stream) (void)hipStreamDestroy(h->la_stream);
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
     if (h->ev_rest) (void)hipEventDestroy(h->ev_rest);
+    if (h->ev_pq) (void)hipEventDestroy(h->ev_pq);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }

@@ -1925,7 +1925,11 @@ constexpr int kSsKC = 16;               // inner indices per LDS slice
 // mode selects the tiles of each level: all (0); those in its first sscrit
 // tile rows or columns, which hold every target of the next wave's blocks
 // (1: tile rows 0 .. sscrit - 1 whole, then the first sscrit columns of the
-// later rows); the others (2: the square of later rows and columns).  The
+// later rows); the others (2: the square of later rows and columns); of
+// mode 1, the square of the first sscrit rows and columns, which holds the
+// next wave's diagonal blocks (3), and the two bands beside it, which hold
+// its panels (4: rows 0 .. sscrit - 1 times the later columns, then the later
+// rows times the first sscrit columns).  The
 // 64 x 64 tiles are compiled for four resident workgroups per CU (110
 // registers, no spills; LDS allows four): 13 % faster than the three that
 // the unconstrained allocation (144 registers) left room for.  A grid
@@ -1952,10 +1956,10 @@ __device__ __forceinline__ void ssssm_tile(int64_t bid, int64_t total, double *_
     int lo = 0, hi = nlev - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (rtile[3 * mid + mode] <= bid) lo = mid; else hi = mid - 1;
+        if (rtile[5 * mid + mode] <= bid) lo = mid; else hi = mid - 1;
     }
     const LevelDev L = levels[rlev[lo]];
-    const int tile = (int)(bid - rtile[3 * lo + mode]);
+    const int tile = (int)(bid - rtile[5 * lo + mode]);
     const int m = L.m, kp = (L.kappa + 15) & ~15, nseg = L.seg_end - L.seg_begin;
     const int nt = (m + TT - 1) / TT;
     int ti, tj;
@@ -1972,10 +1976,24 @@ __device__ __forceinline__ void ssssm_tile(int64_t bid, int64_t total, double *_
             ti = nc + q / nc;
             tj = q - (q / nc) * nc;
         }
-    } else {
+    } else if (mode == 2) {
         const int nc = L.sscrit, nr = nt - nc;
         ti = nc + tile / nr;
         tj = nc + tile - (tile / nr) * nr;
+    } else if (mode == 3) {
+        const int nc = L.sscrit;
+        ti = tile / nc;
+        tj = tile - ti * nc;
+    } else {
+        const int nc = L.sscrit, nr = nt - nc;
+        if (tile < nc * nr) {
+            ti = tile / nr;
+            tj = nc + tile - ti * nr;
+        } else {
+            const int q = tile - nc * nr;
+            ti = nc + q / nc;
+            tj = q - (q / nc) * nc;
+        }
     }
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -2143,11 +2161,12 @@ __global__ __launch_bounds__(TT == 64 ? 256 : 64, TT == 64 ? 4 : 1) void k_ssssm
 
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, int mode, int max_groups,
                               hipStream_t s) {
-    const int64_t tiles = mode == 0 ? r.tiles : (mode == 1 ? r.tiles_c : r.tiles_r);
+    const int64_t counts[5] = {r.tiles, r.tiles_c, r.tiles_r, r.tiles_d, r.tiles_pq};
+    const int64_t tiles = counts[mode];
     if (tiles <= 0) return hipSuccess;
     const int nlev = r.end - r.begin;
     const int32_t *rl = d.round_levels + r.begin;
-    const int64_t *rt = d.round_tiles + 3 * (size_t)r.begin;
+    const int64_t *rt = d.round_tiles + 5 * (size_t)r.begin;
     const dim3 g((unsigned)(max_groups > 0 && tiles > max_groups ? max_groups : tiles));
     if (r.tile == 64) {
         if (f32)

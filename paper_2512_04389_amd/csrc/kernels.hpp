@@ -88,8 +88,9 @@ hipError_t launch_panel_solve_wave(const DevPlan &d, const int32_t *lvl, int nle
 hipError_t launch_panel_blk_wave(const DevPlan &d, const int32_t *lvl, int nlev, int max_m, int max_kp,
                                  hipStream_t s);
 // mode: 0 all tiles of the round's levels, 1 those that update the next
-// wave, 2 the rest (see k_ssssm); max_groups > 0 (a multiple of 8) caps the
-// workgroups, which then walk the tiles.
+// wave, 2 the rest, 3 / 4 the next wave's diagonal square / panel bands (see
+// k_ssssm); max_groups > 0 (a multiple of 8) caps the workgroups, which then
+// walk the tiles.
 hipError_t launch_ssssm_round(const DevPlan &d, const RoundInfo &r, bool f32, int mode, int max_groups,
                               hipStream_t s);
 

@@ -90,12 +90,13 @@ bool split_ok(const slu::Analysis &an) {
     std::vector<int32_t> wave_of(an.levels.size(), 0);
     for (size_t wi = 0; wi < an.waves.size(); ++wi)
         for (int32_t q = an.waves[wi].begin; q < an.waves[wi].end; ++q) wave_of[an.wave_levels[q]] = (int32_t)wi;
-    if (an.round_tiles.size() != 3 * an.round_levels.size()) return false;
+    if (an.round_tiles.size() != 5 * an.round_levels.size()) return false;
     for (const slu::RoundInfo &r : an.rounds) {
-        if (r.tiles_c + r.tiles_r != r.tiles) return false;
-        int64_t t = 0, tc = 0, tr = 0;
+        if (r.tiles_c + r.tiles_r != r.tiles || r.tiles_d + r.tiles_pq != r.tiles_c) return false;
+        int64_t t = 0, tc = 0, tr = 0, td = 0, tq = 0;
         for (int32_t q = r.begin; q < r.end; ++q) {
-            if (an.round_tiles[3 * q] != t || an.round_tiles[3 * q + 1] != tc || an.round_tiles[3 * q + 2] != tr)
+            if (an.round_tiles[5 * q] != t || an.round_tiles[5 * q + 1] != tc || an.round_tiles[5 * q + 2] != tr ||
+                an.round_tiles[5 * q + 3] != td || an.round_tiles[5 * q + 4] != tq)
                 return false;
             const int32_t i = an.round_levels[q];
             const slu::LevelDev &L = an.levels[i];
@@ -104,12 +105,14 @@ bool split_ok(const slu::Analysis &an) {
             t += nt * nt;
             tc += nt * nt - (nt - nc) * (nt - nc);
             tr += (nt - nc) * (nt - nc);
+            td += nc * nc;
+            tq += 2 * nc * (nt - nc);
             for (int32_t sgi = L.seg_begin; sgi < L.seg_end; ++sgi) {
                 const slu::Segment &g = an.segs[sgi];
                 if (wave_of[g.blk] == wave_of[i] + 1 && (int64_t)(g.start + g.len) > nc * r.tile) return false;
             }
         }
-        if (t != r.tiles || tc != r.tiles_c || tr != r.tiles_r) return false;
+        if (t != r.tiles || tc != r.tiles_c || tr != r.tiles_r || td != r.tiles_d || tq != r.tiles_pq) return false;
     }
     return true;
 }

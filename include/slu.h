@@ -292,14 +292,13 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
 
 /* Tiled diagonal solves: in slu_solve, slu_solve_transpose and the solves
  * inside slu_solve_refined, a wave whose largest diagonal block has at least
- * min_rows rows (default 256; 0: never), whose blocks were factored by the
+ * min_rows rows (default 64; 0: never), whose blocks were factored by the
  * 32 x 32 tiled GETRF and are either dense (S fills at least half of every
- * block's lower triangle) or all at least min_sparse_rows rows (default 640;
+ * block's lower triangle) or all at least min_sparse_rows rows (default 64;
  * 0: dense blocks only) solves its diagonal blocks tile by tile across the
  * GPU with the inverted diagonal tiles the factorization kept (one launch per
- * tile step, b / 32 + 1 steps); otherwise one workgroup per block walks its
- * column chunks (b / 16 dependent steps, cheaper for sparse blocks of a few
- * hundred rows).  Same results up to rounding.  SLU_ERR_ARG for a negative
+ * pair of 32-row tiles, b / 64 steps rounded up); otherwise one workgroup per
+ * block walks its column chunks (b / 16 dependent steps).  Same results up to rounding.  SLU_ERR_ARG for a negative
  * argument. */
 int slu_set_solve_tiled(slu_handle *h, int min_rows, int min_sparse_rows);
 

@@ -280,7 +280,7 @@ class SparseLU:
         rows.sort(key=lambda r: r["ms"])
         return rows
 
-    def set_solve_tiled(self, min_rows, min_sparse_rows=640):
+    def set_solve_tiled(self, min_rows, min_sparse_rows=64):
         """Tiled diagonal solves for waves with blocks of at least ``min_rows``
         rows (see ``slu_set_solve_tiled``; 0: never)."""
         check(lib.slu_set_solve_tiled(self._h, int(min_rows), int(min_sparse_rows)), "slu_set_solve_tiled")

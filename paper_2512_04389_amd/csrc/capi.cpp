@@ -50,8 +50,8 @@ struct slu_handle {
     // rows use the tiled solve when their blocks were factored by the 32 x 32
     // tiled GETRF (0: never); wave_tinv: per wave, the last factor kept the
     // inverted diagonal tiles
-    int solve_tiled_rows = 256;
-    int solve_tiled_sparse_rows = 640;   // ... and, for blocks under half dense, at least this many
+    int solve_tiled_rows = 64;
+    int solve_tiled_sparse_rows = 64;   // ... and, for blocks under half dense, at least this many
     std::vector<char> wave_tinv;
     // Schur updates of a wave (of one round) that reach only later waves run
     // on a second stream (default priority) while the next wave factors its
@@ -148,14 +148,15 @@ hipError_t upload(void *base, size_t off, const std::vector<T> &v, hipStream_t s
 // factored by the 32 x 32 tiled GETRF (the inverted diagonal tiles are kept),
 // every block has a tiled work region, the wave's largest block reaches the
 // threshold and its blocks are dense (at least half of every block's lower
-// triangle in S: the one-workgroup solve walks only the coupled rows of
-// sparse blocks and wins there).
+// triangle in S) or all reach the sparse-block threshold (the one-workgroup
+// solve walks only the coupled rows of a sparse block, and wins only on small
+// ones).
 bool tiled_solve(const slu_handle *h, size_t wi) {
     const slu::WaveInfo &w = h->an.waves[wi];
     // dense blocks, or blocks large enough (min_sparse_rows) that the
     // one-workgroup walk of their column chunks, a chain of b / 16 steps,
-    // takes longer than the b / 32 + 1 chip-wide tile steps whatever their
-    // density
+    // takes longer than the b / 64 (rounded up) chip-wide tile-pair steps
+    // whatever their density
     const bool worth = w.min_dense_pct >= 50 || w.min_b >= h->solve_tiled_sparse_rows;
     return h->solve_tiled_rows > 0 && wi < h->wave_tinv.size() && h->wave_tinv[wi] && w.min_b > 16 &&
            w.max_b >= h->solve_tiled_rows && worth && w.end - w.begin <= 65535;

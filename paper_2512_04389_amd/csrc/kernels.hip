@@ -2474,13 +2474,19 @@ hipError_t launch_solve_diag_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // tiled GETRF, with the inverted diagonal tiles it kept: for the forward
 // sweep (L, or U^T when transposed) tile t gives x_t = M_t b_t and every
 // later row tile r takes b_r -= A_rt x_t; the backward sweep (U, or L^T)
-// runs the same from the last tile up.  One launch per tile step u = 0..nt,
-// one wave per (level, row tile r): it finalizes x of the tile solved in
-// step u - 1 when r is that tile (nobody reads it in step u), and otherwise
-// forms x of tile u itself from b_u (read-only in step u) and updates its
-// own rows.  M_t is iL_t, iU_t^T, iU_t or iL_t^T; A_rt is the block's tile
-// (r, t), transposed for the transposed solve.  The right-hand sides of a
-// 32-row tile are the 16 columns of 16 x 16 x 4 FP64 MFMA products (nc <= 16).
+// runs the same from the last tile up.  The tiles are taken two at a time,
+// in sweep order: pair p = (t0, t1) gives x_t0 = M_t0 b_t0,
+// x_t1 = M_t1 (b_t1 - A_t1t0 x_t0), and every later row tile r takes
+// b_r -= A_rt0 x_t0 + A_rt1 x_t1.  One launch per pair step u, one wave per
+// (level, row tile r beyond pair u): each wave forms both x of pair u itself
+// from b_t0 and b_t1 (read-only in step u) and updates its own rows.  The
+// wave q = 0 of step u > 0 stores x of pair u - 1 (nobody reads those rows in
+// step u); the last pair, which has no row tile beyond it, is stored by a
+// wave of its own step.  M_t is iL_t, iU_t^T, iU_t or iL_t^T; A_rt is the
+// block's tile (r, t), transposed for the transposed solve.  The right-hand
+// sides of a 32-row tile are the 16 columns of 16 x 16 x 4 FP64 MFMA
+// products (nc <= 16); a product's result layout is also the layout of the
+// operand the next product takes, so x_t0 feeds A_t1t0 x_t0 directly.
 template <bool ONE>
 __global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD1, int64_t offW1,
                                                    const double *__restrict__ slab, const double *__restrict__ work,
@@ -2496,20 +2502,28 @@ __global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD
         b = L.b, r0 = L.r0, offD = L.offD, offW = L.offW;
     }
     const int nt = (b + 31) >> 5;
-    if (u > nt) return;
+    if (2 * u >= nt) return;   // this block's last pair came before step u
     const int q = blockIdx.x;
-    // step u handles tile t (solved now) and finalizes tile tp (solved in u - 1)
-    const int t = fwd ? u : nt - 1 - u;
-    const int tp = fwd ? u - 1 : nt - u;
-    // workgroup q: the finalized tile first (q = 0, when u > 0), then the
-    // tiles that tile t updates, walking away from t
-    int r;
+    // Tiles are counted in sweep order (tile j is j forward, nt - 1 - j
+    // backward).  Workgroup q: pair u - 1 to store (q = 0, when u > 0), then
+    // the row tiles beyond pair u, walking away from it; at the last pair the
+    // first of those stores pair u instead.
     const int q0 = u > 0 ? 1 : 0;
-    if (u > 0 && q == 0)
-        r = tp;
-    else
-        r = fwd ? t + 1 + (q - q0) : t - 1 - (q - q0);
-    if (r < 0 || r >= nt) return;
+    const int nrow = nt - 2 * u - 2;
+    int pair, jr;   // pair solved; row tile updated in sweep order (-1: store the pair)
+    if (u > 0 && q == 0) {
+        pair = u - 1, jr = -1;
+    } else {
+        const int j = q - q0;
+        if (j >= (nrow > 0 ? nrow : 1)) return;
+        pair = u, jr = nrow > 0 ? 2 * u + 2 + j : -1;
+    }
+    const int j0 = 2 * pair;
+    const bool has1 = j0 + 1 < nt;   // false only for a single last tile
+    const int t0 = fwd ? j0 : nt - 1 - j0;
+    // a missing second tile is read as t0 again (in range) and never stored
+    const int t1 = has1 ? (fwd ? j0 + 1 : nt - 2 - j0) : t0;
+    const int r = jr >= 0 ? (fwd ? jr : nt - 1 - jr) : t0;   // row tile, or t0 again when storing
     const double *__restrict__ D = slab + offD;
     const double *__restrict__ Inv = work + offW + 128 * (size_t)b;
     const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
@@ -2525,85 +2539,101 @@ __global__ __launch_bounds__(64) void k_solve_tile(int b1, int r01, int64_t offD
     // element (i, k) of the operator applied, i.e. iL / iU, transposed for
     // the transposed solve
     const bool mtr = use_l ? trans != 0 : trans == 0;
-    auto mload = [&](int s2, int i, int k) -> double {
-        const double *Mb = Inv + (size_t)s2 * 2048 + (use_l ? 0 : 1024);
-        return mtr ? Mb[k * 32 + i] : Mb[i * 32 + k];
+    // rows of tile s in result layout: half h, lane (li, g), element e ->
+    // row 16 h + g + 4 e, right-hand side li (also the B-operand layout of a
+    // product over tile s: step kk, lane (li, g) -> row 16 hk + 4 kk + g)
+    auto load_b = [&](int s, double4_t(&v)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[h][e] = Xc[min(32 * s + 16 * h + g + 4 * e, b - 1)];
     };
-    // x of tile s2 (32 rows) = M b_s2 in result layout: half h, lane (li, g),
-    // element r -> row 16 h + g + 4 r, right-hand side li
-    auto solve_tile = [&](int s2, double4_t (&x)[2]) {
-        double bb[2][4];
+    auto load_m = [&](int s, double(&m)[2][2][4]) {
+        const double *Mb = Inv + (size_t)s * 2048 + (use_l ? 0 : 1024);
 #pragma unroll
-        for (int hk = 0; hk < 2; ++hk)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                bb[hk][kk] = Xc[min(32 * s2 + 16 * hk + 4 * kk + g, b - 1)];
-            }
+            for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int i = 16 * h + li, k = 16 * hk + 4 * kk + g;
+                    m[h][hk][kk] = mtr ? Mb[k * 32 + i] : Mb[i * 32 + k];
+                }
+    };
+    // -A_rt (i, k) = -D(32 r + i, 32 t + k), or -D(32 t + k, 32 r + i) for
+    // the transposed solve; zero past b, and everywhere when on == 0
+    auto load_a = [&](int rr, int tt, double on, double(&a)[2][2][4]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ri = 32 * rr + 16 * h + li;
+#pragma unroll
+            for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int ck = 32 * tt + 16 * hk + 4 * kk + g;
+                    const size_t ric = (size_t)min(ri, b - 1), ckc = (size_t)min(ck, b - 1);
+                    a[h][hk][kk] = (trans ? D[ric * b + ckc] : D[ckc * b + ric]) * ((ri < b && ck < b) ? -on : 0.0);
+                }
+        }
+    };
+    // x = m bin
+    auto apply_m = [&](const double(&m)[2][2][4], const double4_t(&bin)[2], double4_t(&x)[2]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             x[h] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int hk = 0; hk < 2; ++hk)
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const double a = mload(s2, 16 * h + li, 16 * hk + 4 * kk + g);
-                    x[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[hk][kk], x[h], 0, 0, 0);
-                }
+                for (int kk = 0; kk < 4; ++kk)
+                    x[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[h][hk][kk], bin[hk][kk], x[h], 0, 0, 0);
         }
     };
-    if (u > 0 && r == tp) {
-        double4_t x[2];
-        solve_tile(tp, x);
+    // acc += a x
+    auto apply_a = [&](const double(&a)[2][2][4], const double4_t(&x)[2], double4_t(&acc)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][hk][kk], x[hk][kk], acc[h], 0, 0, 0);
+    };
+    auto store = [&](int s, const double4_t(&v)[2]) {
         if (rhs_ok) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = 32 * tp + 16 * h + g + 4 * e;
-                    if (row < b) Xc[row] = x[h][e];
+                    const int row = 32 * s + 16 * h + g + 4 * e;
+                    if (row < b) Xc[row] = v[h][e];
                 }
         }
-        return;
-    }
-    if (u >= nt) return;
-    // b_r -= A_rt x_t: A_rt(i, k) = D(32 r + i, 32 t + k), or D(32 t + k, 32 r + i)
-    // for the transposed solve.  Its operands (and b_r) are loaded before
-    // tile t is solved, so that both memory round trips overlap.
-    double av[2][2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int ri = 32 * r + 16 * h + li;
-#pragma unroll
-        for (int hk = 0; hk < 2; ++hk)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int ck = 32 * t + 16 * hk + 4 * kk + g;
-                const size_t ric = (size_t)min(ri, b - 1), ckc = (size_t)min(ck, b - 1);
-                av[h][hk][kk] = (trans ? D[ric * b + ckc] : D[ckc * b + ric]) * ((ri < b && ck < b) ? -1.0 : 0.0);
-            }
-    }
-    double4_t acc[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[h][e] = Xc[min(32 * r + 16 * h + g + 4 * e, b - 1)];
-    double4_t x[2];
-    solve_tile(t, x);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int hk = 0; hk < 2; ++hk)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][hk][kk], x[hk][kk], acc[h], 0, 0, 0);
-    if (rhs_ok) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = 32 * r + 16 * h + g + 4 * e;
-                if (row < b) Xc[row] = acc[h][e];
-            }
+    };
+    double4_t bt0[2], bt1[2], br[2];
+    double m0[2][2][4], m1[2][2][4], a10[2][2][4], ar0[2][2][4], ar1[2][2][4];
+    load_b(t0, bt0);
+    load_b(t1, bt1);
+    load_m(t0, m0);
+    load_m(t1, m1);
+    load_a(t1, t0, has1 ? 1.0 : 0.0, a10);
+    load_b(r, br);
+    load_a(r, t0, 1.0, ar0);
+    load_a(r, t1, 1.0, ar1);
+    // keep every load ahead of the products: one memory round trip in all
+    __builtin_amdgcn_sched_barrier(0);
+    double4_t x0[2], x1[2];
+    apply_m(m0, bt0, x0);
+    apply_a(a10, x0, bt1);
+    apply_m(m1, bt1, x1);
+    // formed by the storing wave too (on its own rows, and not stored), so
+    // that no load is left for a branch
+    apply_a(ar0, x0, br);
+    apply_a(ar1, x1, br);
+    if (jr >= 0) {
+        store(r, br);
+    } else {
+        store(t0, x0);
+        if (has1) store(t1, x1);
     }
 }
 
@@ -2611,10 +2641,11 @@ hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev
                                   int trans, const LevelDev *one, hipStream_t s) {
     if (nlev <= 0 || nlev > 65535) return hipErrorInvalidValue;
     const int nt = (max_b + 31) / 32;
-    for (int u = 0; u <= nt; ++u) {
-        // rows handled in step u: the finalized tile plus the tiles it updates
-        const unsigned gx = (unsigned)(u == 0 ? nt - 1 : (nt - u > 1 ? nt - u : 1));
-        if (gx == 0) continue;
+    for (int u = 0; 2 * u < nt; ++u) {
+        // waves of step u: pair u - 1 stored, then the row tiles beyond pair
+        // u (or, at the last pair, the wave that stores it)
+        const int rows = nt - 2 * u - 2;
+        const unsigned gx = (unsigned)((u > 0 ? 1 : 0) + (rows > 1 ? rows : 1));
         if (nlev == 1 && one)
             hipLaunchKernelGGL(k_solve_tile<true>, dim3(gx, 1), dim3(64), 0, s, one->b, one->r0, one->offD, one->offW,
                                d.slab, d.tgetrf, d.scratch, d.n, u, fwd ? 1 : 0, trans, nc, d.levels, lvl);

@@ -43,6 +43,13 @@ CASES = {
                                         dict(ordering="grid_nd", grid_dims=(14, 14, 14), blocking="regular",
                                              block_size=300)),
 }
+# blocks of one to four 32-row tiles (tiles are solved in pairs: a single
+# tile, one pair, a pair and a single last tile, two pairs), several blocks
+# per wave, ragged last blocks
+for _b, _k in ((20, 24), (40, 24), (70, 24), (100, 30)):
+    CASES["lap2d-%d-regular-%d" % (_k, _b)] = (
+        lambda b=_b, k=_k: (synth.laplacian_2d(k), dict(ordering="grid_nd", grid_dims=(k, k, 1), blocking="regular",
+                                                        block_size=b)))
 
 
 @pytest.mark.parametrize("case", sorted(CASES))

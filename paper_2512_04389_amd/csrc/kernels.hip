@@ -2666,7 +2666,10 @@ hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // products (columns past nc are zero); the four waves split the inner index
 // in interleaved 4-deep steps, with its W values staged in LDS 256 at a time
 // (column-major, padded against bank conflicts); the four partial sums are
-// added in LDS in a fixed order.
+// added in LDS in a fixed order.  Loads go out in batches from clamped
+// addresses (values past the slice masked by a product), so that a slice
+// costs a few memory round trips instead of one per step and right-hand
+// side.
 constexpr int kUpdSlice = 256;
 
 __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ slab,
@@ -2690,23 +2693,40 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
         for (int t0 = 0; t0 < kap; t0 += kUpdSlice) {
             const int nt = min(kUpdSlice, kap - t0);
+            // thread tid stages inner index tid of the slice for every
+            // right-hand side (kUpdSlice == the workgroup size)
+            const size_t kt = (size_t)L.r0 + K[t0 + min(tid, nt - 1)];
+            double xv[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) xv[c] = W[kt + (size_t)min(c, nc - 1) * n];
             __syncthreads();
-            for (int e = tid; e < nc * kUpdSlice; e += 256) {
-                const int c = e / kUpdSlice, t = e - c * kUpdSlice;
-                if (t < nt) xk[c * XL + t] = W[L.r0 + K[t0 + t] + (size_t)c * n];
+            if (tid < nt) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c < nc) xk[c * XL + tid] = xv[c];
             }
             __syncthreads();
-            // step j: inner index t = 16 j + 4 wave + g in lane group g
+            // step j: inner index t = 16 j + 4 wave + g in lane group g;
+            // eight steps' operands load before their products
             const int nst = (nt + 15) >> 4;
-            for (int j = 0; j < nst; ++j) {
-                const int t = 16 * j + 4 * wave + g;
-                const bool tok = t < nt;
-                const size_t tc = (size_t)(t0 + min(t, nt - 1));
-                const double msk = tok ? 1.0 : 0.0;
-                const double a0 = X[tc * m + ra0] * msk, a1 = X[tc * m + ra1] * msk;
-                const double bv = tok ? xk[li * XL + t] : 0.0;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1, 0, 0, 0);
+            for (int j0 = 0; j0 < nst; j0 += 8) {
+                double a0[8], a1[8], bv[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int t = 16 * (j0 + jj) + 4 * wave + g;
+                    const int tcl = min(t, nt - 1);
+                    const size_t tc = (size_t)(t0 + tcl);
+                    const double msk = t < nt ? 1.0 : 0.0;
+                    a0[jj] = X[tc * m + ra0] * msk;
+                    a1[jj] = X[tc * m + ra1] * msk;
+                    bv[jj] = xk[li * XL + tcl] * msk;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[jj], bv[jj], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[jj], bv[jj], acc1, 0, 0, 0);
+                }
             }
         }
         // acc_h[r] of lane (li, g): row 16 h + g + 4 r of the tile, column li
@@ -2730,7 +2750,10 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
 // W[r0 + K_i[t]] -= sum_a X[a, t] W[rows_i[a]]   (X = Qt_i, or P_i when transposed)
 // for the levels of one wave (each writes only its own block's rows):
 // blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) the column
-// t, blockIdx.z the right-hand side; one wave reduces over a.
+// t, blockIdx.z the right-hand side; one wave reduces over a, eight rows per
+// lane at a time (their indices, then the gathered values, load together:
+// two memory round trips per 512 rows) into four partial sums added in a
+// fixed order.
 __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ slab, const LevelDev *__restrict__ levels,
                                                    const int32_t *__restrict__ lvl,
                                                    const int32_t *__restrict__ Kidx,
@@ -2744,8 +2767,21 @@ __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ sl
     const double *__restrict__ Wc = W + (size_t)c * n;
     for (int t = blockIdx.y; t < L.kappa; t += gridDim.y) {
         const double *__restrict__ X = slab + (trans ? L.offP : L.offQ) + (size_t)t * m;
-        double acc = 0.0;
-        for (int a = threadIdx.x; a < m; a += 64) acc += X[a] * Wc[R[a]];
+        double part[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int a0 = 0; a0 < m; a0 += 512) {
+            int32_t ri[8];
+            double xv[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const int a = a0 + 64 * jj + (int)threadIdx.x;
+                const int ac = min(a, m - 1);
+                ri[jj] = R[ac];
+                xv[jj] = X[ac] * (a < m ? 1.0 : 0.0);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) part[jj & 3] += xv[jj] * Wc[ri[jj]];
+        }
+        double acc = (part[0] + part[1]) + (part[2] + part[3]);
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (threadIdx.x == 0) W[L.r0 + Kidx[L.Koff + t] + (size_t)c * n] -= acc;
     }

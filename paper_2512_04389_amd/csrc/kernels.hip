@@ -2667,9 +2667,9 @@ hipError_t launch_solve_tile_wave(const DevPlan &d, const int32_t *lvl, int nlev
 // in interleaved 4-deep steps, with its W values staged in LDS 256 at a time
 // (column-major, padded against bank conflicts); the four partial sums are
 // added in LDS in a fixed order.  Loads go out in batches from clamped
-// addresses (values past the slice masked by a product), so that a slice
-// costs a few memory round trips instead of one per step and right-hand
-// side.
+// addresses (values past the slice masked by a product), sized to the
+// slice, so that it costs a few memory round trips instead of one per step
+// and right-hand side.
 constexpr int kUpdSlice = 256;
 
 __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ slab,
@@ -2695,10 +2695,12 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
             const int nt = min(kUpdSlice, kap - t0);
             // thread tid stages inner index tid of the slice for every
             // right-hand side (kUpdSlice == the workgroup size)
-            const size_t kt = (size_t)L.r0 + K[t0 + min(tid, nt - 1)];
             double xv[16];
+            if (tid < nt) {
+                const size_t kt = (size_t)L.r0 + K[t0 + tid];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) xv[c] = W[kt + (size_t)min(c, nc - 1) * n];
+                for (int c = 0; c < 16; ++c) xv[c] = W[kt + (size_t)min(c, nc - 1) * n];
+            }
             __syncthreads();
             if (tid < nt) {
 #pragma unroll
@@ -2707,12 +2709,14 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
             }
             __syncthreads();
             // step j: inner index t = 16 j + 4 wave + g in lane group g;
-            // eight steps' operands load before their products
+            // the operands of NS steps load before their products: eight
+            // at a time, then four for the rest
             const int nst = (nt + 15) >> 4;
-            for (int j0 = 0; j0 < nst; j0 += 8) {
-                double a0[8], a1[8], bv[8];
+            auto steps = [&](auto ns, int j0) {
+                constexpr int NS = decltype(ns)::value;
+                double a0[NS], a1[NS], bv[NS];
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
+                for (int jj = 0; jj < NS; ++jj) {
                     const int t = 16 * (j0 + jj) + 4 * wave + g;
                     const int tcl = min(t, nt - 1);
                     const size_t tc = (size_t)(t0 + tcl);
@@ -2723,11 +2727,14 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
+                for (int jj = 0; jj < NS; ++jj) {
                     acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[jj], bv[jj], acc0, 0, 0, 0);
                     acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[jj], bv[jj], acc1, 0, 0, 0);
                 }
-            }
+            };
+            int j0 = 0;
+            for (; j0 + 8 <= nst; j0 += 8) steps(std::integral_constant<int, 8>{}, j0);
+            for (; j0 < nst; j0 += 4) steps(std::integral_constant<int, 4>{}, j0);
         }
         // acc_h[r] of lane (li, g): row 16 h + g + 4 r of the tile, column li
 #pragma unroll
@@ -2751,9 +2758,9 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ s
 // for the levels of one wave (each writes only its own block's rows):
 // blockIdx.x picks the level, blockIdx.y (striding by gridDim.y) the column
 // t, blockIdx.z the right-hand side; one wave reduces over a, eight rows per
-// lane at a time (their indices, then the gathered values, load together:
-// two memory round trips per 512 rows) into four partial sums added in a
-// fixed order.
+// lane at a time and two for the rest (their indices, then the gathered
+// values, load together: two memory round trips per 512 rows) into four
+// partial sums added in a fixed order.
 __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ slab, const LevelDev *__restrict__ levels,
                                                    const int32_t *__restrict__ lvl,
                                                    const int32_t *__restrict__ Kidx,
@@ -2768,19 +2775,24 @@ __global__ __launch_bounds__(64) void k_bwd_update(const double *__restrict__ sl
     for (int t = blockIdx.y; t < L.kappa; t += gridDim.y) {
         const double *__restrict__ X = slab + (trans ? L.offP : L.offQ) + (size_t)t * m;
         double part[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int a0 = 0; a0 < m; a0 += 512) {
-            int32_t ri[8];
-            double xv[8];
+        // NS rows per lane at a time: eight, then two for the rest
+        auto rows = [&](auto ns, int a0) {
+            constexpr int NS = decltype(ns)::value;
+            int32_t ri[NS];
+            double xv[NS];
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
+            for (int jj = 0; jj < NS; ++jj) {
                 const int a = a0 + 64 * jj + (int)threadIdx.x;
                 const int ac = min(a, m - 1);
                 ri[jj] = R[ac];
                 xv[jj] = X[ac] * (a < m ? 1.0 : 0.0);
             }
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) part[jj & 3] += xv[jj] * Wc[ri[jj]];
-        }
+            for (int jj = 0; jj < NS; ++jj) part[jj & 3] += xv[jj] * Wc[ri[jj]];
+        };
+        int a0 = 0;
+        for (; a0 + 512 <= m; a0 += 512) rows(std::integral_constant<int, 8>{}, a0);
+        for (; a0 < m; a0 += 128) rows(std::integral_constant<int, 2>{}, a0);
         double acc = (part[0] + part[1]) + (part[2] + part[3]);
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (threadIdx.x == 0) W[L.r0 + Kidx[L.Koff + t] + (size_t)c * n] -= acc;

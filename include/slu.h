@@ -297,9 +297,10 @@ int slu_autotune(slu_handle *h, const double *values, int reps, slu_tune_entry *
  * block's lower triangle) or all at least min_sparse_rows rows (default 64;
  * 0: dense blocks only) solves its diagonal blocks tile by tile across the
  * GPU with the inverted diagonal tiles the factorization kept (one launch per
- * pair of 32-row tiles, b / 64 steps rounded up); otherwise one workgroup per
- * block walks its column chunks (b / 16 dependent steps).  Same results up to rounding.  SLU_ERR_ARG for a negative
- * argument. */
+ * pair of 32-row tiles, b / 64 steps rounded up); otherwise, and for waves
+ * with a block of 16 rows or fewer, one workgroup per block walks its column
+ * chunks (b / 16 dependent steps).  Same results up to rounding.  SLU_ERR_ARG
+ * for a negative argument. */
 int slu_set_solve_tiled(slu_handle *h, int min_rows, int min_sparse_rows);
 
 /* Lookahead of the Schur updates (Algorithm 1's SSSSM; the level order of
